@@ -1,0 +1,185 @@
+/*
+ * gedmg -- gradient-enhanced damage with input-convex-network constitutive
+ * laws: quadrature-point update, element residual/tangent and CSR assembly on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The model (paper: "A Differentiable Framework for Gradient Enhanced Damage
+ * with Physics-Augmented Neural Networks in JAX-FEM"):
+ *   Psi(F, phi, grad phi, kappa) = f_d(kappa) psi_e(C) + c_d/2 grad phi.C^-1.grad phi
+ *                                  + beta_d/2 (phi - kappa)^2            (Eq. dd_3)
+ *   psi_e = mu_e [N(x) - N(0) - n0 (J-1)] + lambda_e (J + 1/J - 2)^2     (Eq. dd_0)
+ *   x = (J^-2/3 I1 - 3, I2^3/(9 J^4) - 3, J - 1),  n0 = dN/dx_3 at x = 0
+ *   f_d = exp(-eta_d <kappa - kappa_d>_+)                  (Eq. degradation_function)
+ *   q = psi_e + gamma_d beta_d (phi - kappa)/(eta_d f_d)   (Eqs. q_q_loc_q_nloc, ostwald_potential)
+ *   yield: N^_kappa(q) - kappa <= 0, N^_kappa(q) = N_kappa(q) - N_kappa(0)  (Eqs. Gq_NN, dd_7)
+ * residual (Sec. 3.1): r_u,a = sum_q P grad N_a Jw, R_phi,a = sum_q (Y.grad N_a - Y N_a) Jw;
+ * monolithic tangent (Sec. 3.2): history update inside every Newton iteration,
+ * its sensitivities part of the consistent tangent.
+ *
+ * Conventions
+ *   - 2-D: Q4 plane strain (unit thickness, F33 = 1); 3-D: Hex8.  Node order
+ *     counter-clockwise (Q4) / standard (Hex8).  Quadrature: 2x2 / 2x2x2 Gauss,
+ *     qp q at the natural coordinates of node q divided by sqrt(3), weight 1.
+ *   - dofs interleaved node-major: dof(node, c) = node*(dim+1) + c, c < dim the
+ *     displacement, c == dim the nonlocal damage phi.
+ *   - nodal fields structure-of-arrays: u[dim][n_nodes], phi[n_nodes];
+ *     history kappa[n_elems][nqp] (nqp = 4 or 8).
+ *   - ICNN raw parameters (Sec. 4.2.1, Amos-type input-convex network):
+ *       z1 = s(W0 x + b0); z_{k+1} = s(Wz_k z_k + Wx_k x + b_k); N = wz.z_L + wx.x + b
+ *     with s = softplus; Wz_k, wz are softplus(raw); the weights multiplying
+ *     input i (column i of W0 and Wx_k, wx[i]) are softplus(raw) when bit i of
+ *     monotone_mask is set, raw otherwise.  Flat order: W0 (width x n_in,
+ *     row-major), b0, then per hidden->hidden layer Wz (width x width), Wx
+ *     (width x n_in), b, then wz (width), wx (n_in), b_out.
+ *
+ * Memory and streams
+ *   - Setup data passed to gedmg_create / gedmg_set_params are HOST pointers;
+ *     the library copies them.  Every per-call array of gedmg_assemble,
+ *     gedmg_newton_step and gedmg_adjoint is a DEVICE pointer on the context's
+ *     device, owned by the caller, FP64 unless stated, contiguous.
+ *   - Work is ordered on the HIP stream given to gedmg_create.  A call returns
+ *     after enqueueing, except when it must hand a host report back
+ *     (newton_step, adjoint), which synchronise the stream.
+ *
+ * Errors: every call returns 0 on success or a negative GEDMG_E_* code;
+ * gedmg_last_error() gives a message.  On error the outputs are unspecified,
+ * except that gedmg_newton_step leaves u, phi and kappa at their input values.
+ */
+#ifndef GEDMG_H
+#define GEDMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gedmg_ctx gedmg_ctx;
+
+enum {
+  GEDMG_OK = 0,
+  GEDMG_E_ARG = -1,            /* invalid argument (null pointer, bad size, bad enum) */
+  GEDMG_E_SHAPE = -2,          /* mesh / network shape not supported */
+  GEDMG_E_NONFINITE = -3,      /* NaN or Inf in a residual or solution */
+  GEDMG_E_LOCAL_NOCONV = -4,   /* history update did not converge in max_local iterations */
+  GEDMG_E_NEWTON_NOCONV = -5,  /* global Newton did not converge in max_newton iterations */
+  GEDMG_E_LINSOLVE = -6,       /* Krylov solver failed (breakdown or max iterations) */
+  GEDMG_E_HIP = -7,            /* HIP runtime error */
+  GEDMG_E_NOMEM = -8,          /* device allocation failed */
+  GEDMG_E_JNONPOS = -9         /* det F <= 0 at a quadrature point */
+};
+
+enum { GEDMG_FP64 = 0, GEDMG_BF16 = 1, GEDMG_FP16 = 2 };
+
+typedef struct {
+  int32_t dim;          /* 2 (Q4 plane strain) or 3 (Hex8) */
+  int32_t n_nodes, n_elems;
+  const double* X;      /* host, [dim][n_nodes] reference coordinates */
+  const int32_t* conn;  /* host, [n_elems][nen], nen = 4 or 8 */
+} gedmg_mesh;
+
+typedef struct {
+  double mu_e, lambda_e;  /* energy scale and volumetric modulus (Eq. dd_0) */
+  double eta_d, kappa_d;  /* degradation rate and threshold (Eq. degradation_function) */
+  double c_d, beta_d;     /* gradient and penalty parameters (Sec. 4.1) */
+  double gamma_d;         /* factor of q_nloc (Eq. ostwald_potential), 1 in the paper's chain rule */
+} gedmg_material;
+
+typedef struct {
+  int32_t n_in;           /* 3 for the energy network, 1 for the yield network */
+  int32_t width;          /* hidden width: energy 16, 32 or 64; yield 16 or 32 */
+  int32_t n_hidden;       /* number of hidden layers (1..3) */
+  int32_t monotone_mask;  /* energy: 3 (I1G, I2G); yield: 1 */
+  const double* theta;    /* host, raw parameters in the order described above */
+} gedmg_icnn;
+
+typedef struct {
+  int32_t n;              /* number of prescribed dofs */
+  const int32_t* dof;     /* device, [n] dof indices (no duplicates) */
+  const double* value;    /* device, [n] prescribed values */
+} gedmg_dirichlet;
+
+typedef struct {
+  int32_t max_newton;     /* global Newton iterations (default 25) */
+  int32_t max_krylov;     /* Krylov iterations per linear solve (default 20000) */
+  int32_t max_local;      /* history-update iterations (default 100, as in the paper's notched plate) */
+  double newton_rtol;     /* ||R_f|| <= max(newton_rtol * max(1, ||R_f^0||), newton_atol) */
+  double newton_atol;
+  double krylov_rtol;     /* relative residual of each linear solve (default 1e-12) */
+} gedmg_solver_opts;
+
+typedef struct {
+  int32_t newton_iters;       /* assemblies - 1 */
+  int32_t krylov_iters_total;
+  int32_t n_yielded_qp;       /* quadrature points whose history grew in the accepted state */
+  int32_t status;             /* same code as the return value */
+  double res_norm[32];        /* ||R_f|| per Newton iteration (first 32) */
+  double reaction;            /* sum of R over the reaction dofs given to newton_step, 0 if none */
+} gedmg_newton_report;
+
+typedef struct {
+  int32_t n_checkpoints, recomputed_steps, newton_iters_total, krylov_iters_total;
+  double t_forward_s, t_reverse_s;
+} gedmg_adjoint_report;
+
+/* Message for the last failure on this context (never NULL). */
+const char* gedmg_last_error(const gedmg_ctx* ctx);
+
+/* Build a context: copies the mesh, builds the CSR pattern of the (dim+1)^2
+ * node-pair blocks, the element colouring and the element -> CSR offset map,
+ * and uploads the effective network weights.  hip_stream may be NULL (the
+ * null stream).  Returns GEDMG_E_SHAPE for widths other than 16/32/64,
+ * energy n_in != 3, yield n_in != 1 or n_hidden outside 1..3. */
+int gedmg_create(gedmg_ctx** ctx, const gedmg_mesh* mesh, const gedmg_material* mat,
+                 const gedmg_icnn* energy, const gedmg_icnn* yield, void* hip_stream);
+int gedmg_destroy(gedmg_ctx* ctx);
+
+/* Replace the raw network parameters (same architecture; host pointers; either
+ * may be NULL to keep it).  Stream-ordered. */
+int gedmg_set_params(gedmg_ctx* ctx, const double* theta_energy, const double* theta_yield);
+
+/* The library-owned CSR pattern (device pointers, valid until destroy):
+ * rowptr[n_rows+1], col[nnz], columns sorted in each row. */
+int gedmg_csr(gedmg_ctx* ctx, int64_t* n_rows, int64_t* nnz, const int32_t** rowptr,
+              const int32_t** col);
+
+/* One assembly at the state (u, phi) with history kappa_n (Sec. 3.1-3.2):
+ * R[ndof] = global residual (internal forces; every row, Dirichlet rows
+ * included), K_vals[nnz] = consistent tangent in the CSR pattern (NULL:
+ * residual only, skips the tangent), kappa_trial[n_elems][nqp] = history after
+ * the local update.  precision selects the arithmetic of the energy-network
+ * layer products: GEDMG_FP64, or GEDMG_BF16 / GEDMG_FP16 matrix-core products
+ * with FP32 accumulation (everything else stays FP64).
+ * GEDMG_E_LOCAL_NOCONV / GEDMG_E_JNONPOS are reported by a later synchronising
+ * call (gedmg_status) because assembly does not synchronise. */
+int gedmg_assemble(gedmg_ctx* ctx, const double* u, const double* phi, const double* kappa_n,
+                   int precision, double* R, double* K_vals, double* kappa_trial);
+
+/* Diagnostic: the energy-network jet at given inputs, in the arithmetic
+ * selected by precision (used by the tests and by the mixed-precision error
+ * report).  x: device [n][3] inputs (I1G - 3, I2G - 3, J - 1); jet: device
+ * [n][10] = N(x) - N(0), dN/dx (3), d2N/dx2 (xx, yy, zz, xy, xz, yz). */
+int gedmg_energy_jet(gedmg_ctx* ctx, const double* x, int64_t n, int precision, double* jet);
+
+/* Synchronise the stream and return the sticky device status of the last
+ * assemblies (GEDMG_OK, GEDMG_E_LOCAL_NOCONV or GEDMG_E_JNONPOS), then clear it. */
+int gedmg_status(gedmg_ctx* ctx);
+
+/* One load step of the monolithic scheme: sets the prescribed dofs, then
+ * Newton on the free dofs, starting from the (u, phi) passed in (the caller's
+ * predictor), with a Jacobi-preconditioned Krylov solve of K_ff d = -R_f per
+ * iteration (CG; BiCGStab when CG breaks down on a non-symmetric or
+ * indefinite tangent).  precision != GEDMG_FP64 uses the mixed-precision
+ * tangent with the FP64 residual (iterative refinement).  On success u, phi
+ * hold the converged state and kappa the committed history kappa_{n+1}; on
+ * failure all three are restored.  reaction_dofs (device, may be NULL when
+ * n_reaction == 0) selects the rows summed into report->reaction. */
+int gedmg_newton_step(gedmg_ctx* ctx, const gedmg_dirichlet* bc, const gedmg_solver_opts* opts,
+                      int precision, double* u, double* phi, double* kappa,
+                      const int32_t* reaction_dofs, int32_t n_reaction,
+                      gedmg_newton_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEDMG_H */

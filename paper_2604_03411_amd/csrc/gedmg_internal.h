@@ -1,0 +1,149 @@
+// Internal declarations shared by the gedmg runtime and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gedmg.h"
+
+namespace gedmg {
+
+constexpr int kMaxHidden = 3;
+
+// Offsets of one network's arrays inside a packed double buffer.  The packed
+// buffer holds the *effective* weights (softplus applied where the ICNN
+// constraints require it), followed by reference-state constants.
+struct NetLayout {
+  int n_in = 0, H = 0, L = 0, mask = 0;
+  int W0 = 0, b0 = 0;                              // [H][n_in], [H]
+  int Wz[kMaxHidden] = {0}, Wx[kMaxHidden] = {0}, b[kMaxHidden] = {0};  // hidden k=1..L-1 at [k]
+  int wz = 0, wx = 0, bout = 0;
+  int a0 = 0, s0 = 0, sb0 = 0;                     // [L][H]: pre-activation at x = 0 and its logistic pair
+  int total = 0;
+  int n_raw = 0;
+};
+
+// Packed order: W0[H][n_in], b0[H]; per hidden->hidden layer k = 1..L-1:
+// Wz[H][H], Wx[H][n_in], b[H]; then wz[H], wx[n_in], b_out; then the
+// reference-state constants a0, s0 = logistic(a0), sb0 = logistic(-a0), each
+// [L][H] (pre-activations of every layer at x = 0).
+__host__ __device__ inline NetLayout make_layout_hd(int n_in, int H, int L, int mask) {
+  NetLayout l;
+  l.n_in = n_in; l.H = H; l.L = L; l.mask = mask;
+  int o = 0;
+  l.W0 = o; o += H * n_in;
+  l.b0 = o; o += H;
+  for (int k = 1; k < L; ++k) {
+    l.Wz[k] = o; o += H * H;
+    l.Wx[k] = o; o += H * n_in;
+    l.b[k] = o; o += H;
+  }
+  l.wz = o; o += H;
+  l.wx = o; o += n_in;
+  l.bout = o; o += 1;
+  l.n_raw = o;
+  l.a0 = o; o += L * H;
+  l.s0 = o; o += L * H;
+  l.sb0 = o; o += L * H;
+  l.total = o;
+  return l;
+}
+
+// Host-side reference-state quantities of a network.
+struct NetRef {
+  double N0 = 0.0;   // N(0)
+  double n0 = 0.0;   // dN/dx_{n_in-1} at 0 (energy: derivative w.r.t. J - 1)
+};
+
+// Fill `packed` (size layout.total) from raw parameters; returns N(0), n0.
+NetRef pack_network(const NetLayout& lay, const double* raw, std::vector<double>& packed);
+
+struct Material {
+  double mu, lam, eta, kd, c, beta, gamma;
+};
+
+// Arguments of the quadrature-input kernel and the energy-network jet kernel.
+struct JetArgs {
+  const double* x;       // [nq][3] network inputs (I1G-3, I2G-3, J-1)
+  double* jet;           // [nq][10]: N(x)-N(0), dN/dx (3), d2N/dx2 (xx,yy,zz,xy,xz,yz)
+  const double* net;     // packed effective network (double)
+  const uint16_t* w16;   // [L-1][H][H+8] low-precision copies of Wz (bf16 or fp16 bits)
+  int nq;
+  int L;
+  int with_hessian;
+};
+
+struct KinArgs {
+  const double* X;       // [dim][n_nodes]
+  const int32_t* conn;   // [n_elems][nen]
+  const double* u;       // [dim][n_nodes]
+  int n_nodes, n_elems;
+  double* x;             // [n_elems*nqp][3]
+  int* status;
+};
+
+struct ElemArgs {
+  const double* X;
+  const int32_t* conn;
+  const int32_t* perm;       // elements sorted by colour
+  const int32_t* blk;        // [n_elems][nen][nen] CSR offset of block (a,b) row 0
+  const int32_t* rowstride;  // [n_nodes] CSR row length of the node's rows
+  const double* u;
+  const double* phi;
+  const double* kappa_n;
+  const double* jet;         // [n_elems*nqp][10]
+  const double* ynet;        // packed yield network
+  double* R;
+  double* K;                 // may be null (residual only)
+  double* kappa_out;
+  int* status;
+  int n_nodes, n_elems;
+  int e_begin, e_end;        // range in perm of the colour being assembled
+  Material m;
+  double n0;                 // energy network dN/dx3 at 0
+  double yN0;                // yield network N(0)
+  int yH, yL;
+  int max_local;
+};
+
+// Kernel launchers (defined in the .hip translation units).
+hipError_t launch_qp_inputs(int dim, const KinArgs& a, hipStream_t s);
+hipError_t launch_energy_jet(int precision, int H, const JetArgs& a, hipStream_t s, int num_cu);
+hipError_t launch_element(int dim, bool tangent, const ElemArgs& a, int ynet_doubles,
+                          hipStream_t s, int num_cu);
+void release_newton_work(gedmg_ctx* c);
+
+}  // namespace gedmg
+
+// The opaque context.
+struct gedmg_ctx {
+  std::string err;
+  hipStream_t stream = nullptr;
+  int device = 0, num_cu = 256;
+  int dim = 0, nen = 0, nqp = 0, nd = 0, n_nodes = 0, n_elems = 0;
+  int64_t ndof = 0, nnz = 0;
+  gedmg::Material mat{};
+  gedmg::NetLayout elay, ylay;
+  gedmg::NetRef eref, yref;
+  std::vector<double> eraw, yraw;      // host copies of the raw parameters
+  std::vector<int> color_begin;        // n_colors + 1 offsets into perm
+  // device buffers owned by the context
+  double* dX = nullptr;
+  int32_t* dconn = nullptr;
+  int32_t* dperm = nullptr;
+  int32_t* dblk = nullptr;
+  int32_t* drowstride = nullptr;
+  int32_t* drowptr = nullptr;
+  int32_t* dcol = nullptr;
+  double* denet = nullptr;             // packed energy network
+  double* dynet = nullptr;             // packed yield network
+  uint16_t* dw_bf16 = nullptr;         // low-precision hidden weights
+  uint16_t* dw_f16 = nullptr;
+  double* dx = nullptr;                // [nq][3]
+  double* djet = nullptr;              // [nq][10]
+  int* dstatus = nullptr;
+  int max_local = 100;                 // history-update iteration limit
+};

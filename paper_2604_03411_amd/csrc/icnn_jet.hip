@@ -1,0 +1,230 @@
+// Energy-network jets on the matrix cores: for every quadrature point,
+// N(x) - N(0), grad_x N and the Hessian d2N/dx2 of the input-convex network
+// (Sec. 4.2.1; the hidden->hidden products are the dense part of the path).
+//
+// Per block: tiles of 16 neurons x 16 quadrature points; wave w owns neuron
+// tile (w % NT) of qp tile (w / NT) in every layer, so per-layer quantities
+// (logistic pairs and input Jacobians) stay in that wave's registers.  The
+// FP64 16x16x4 product returns row (l / 16 + 4 r) of column (l % 16) in
+// accumulator r of lane l, so lane l owns neurons nt*16 + l/16 + 4 r.
+//   forward : 4 columns per qp -- the activation increment dz = z(x) - z(0)
+//             and the three input tangents dz/dx_i;
+//   backward: 1 column -- zbar_k = dN/dz_k;
+//   Hessian : sum_k J_k^T diag(zbar_k s''(a_k)) J_k, J_k = da_k/dx
+// (5 matrix columns per layer instead of the 10 of a forward second-order
+// jet).  Hidden weights are staged once per persistent block in LDS.
+//
+// Activations are carried as increments over the reference state x = 0, so
+// N(x) - N(0) keeps relative precision (delta_softplus, reference constants
+// a0 / s0 / sb0 precomputed per neuron).
+#include "device_common.h"
+#include "gedmg_internal.h"
+
+namespace gedmg {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+template <int H, int L, int WAVES>
+struct JetCfg {
+  static constexpr int NT = H / 16;
+  static constexpr int NQT = WAVES / NT;
+  static constexpr int QB = 16 * NQT;      // quadrature points per batch
+  static constexpr int HP = H + 1;         // padded LDS row (doubles)
+  static constexpr int W_DBL = (L - 1) * H * HP;
+  static constexpr int Z_DBL = 4 * H * QB;
+  static constexpr int X_DBL = QB * 3;
+  static constexpr int LDS_BYTES = 8 * (W_DBL + Z_DBL + X_DBL);
+  static_assert(WAVES % NT == 0, "waves must cover the neuron tiles");
+  static_assert(NT * QB * 10 <= Z_DBL, "reduction buffer aliases the activation buffer");
+};
+
+template <int H, int L, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void jet_f64_kernel(JetArgs a) {
+  using C = JetCfg<H, L, WAVES>;
+  constexpr int NT = C::NT, QB = C::QB, HP = C::HP;
+  extern __shared__ double lds[];
+  double* Wl = lds;
+  double* Zs = Wl + C::W_DBL;
+  double* xs = Zs + C::Z_DBL;
+  double* red = Zs;  // reused after the backward pass
+  const NetLayout lay = make_layout_hd(3, H, L, 3);
+  const double* __restrict__ net = a.net;
+  for (int k = 1; k < L; ++k)
+    for (int idx = threadIdx.x; idx < H * H; idx += blockDim.x)
+      Wl[(k - 1) * H * HP + (idx / H) * HP + (idx % H)] = net[lay.Wz[k] + idx];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nt = wave % NT, qt = wave / NT;
+  const int li = lane & 15, lg = lane >> 4;
+  const int j = qt * 16 + li;  // qp column in the batch
+  const int nbatch = (a.nq + QB - 1) / QB;
+
+  for (int batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
+    const long q0 = (long)batch * QB;
+    for (int idx = threadIdx.x; idx < QB * 3; idx += blockDim.x)
+      xs[idx] = (q0 + idx / 3 < a.nq) ? a.x[q0 * 3 + idx] : 0.0;
+    __syncthreads();
+    const double x[3] = {xs[j * 3], xs[j * 3 + 1], xs[j * 3 + 2]};
+
+    double sS[L][4], sB[L][4];   // logistic pair at a_k, rows r of this lane
+    double Jt[L][4][3];          // da_k/dx
+    double dz[4], zt[4][3];
+
+    // layer 1: a_1 = W0 x + b0 (vector ALU)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = nt * 16 + lg + 4 * r;
+      const double w0 = net[lay.W0 + n * 3], w1 = net[lay.W0 + n * 3 + 1], w2 = net[lay.W0 + n * 3 + 2];
+      const double da = w0 * x[0] + w1 * x[1] + w2 * x[2];
+      dz[r] = delta_softplus<double>(da, net[lay.a0 + n], net[lay.s0 + n], net[lay.sb0 + n],
+                                     sS[0][r], sB[0][r]);
+      Jt[0][r][0] = w0; Jt[0][r][1] = w1; Jt[0][r][2] = w2;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) zt[r][i] = sS[0][r] * Jt[0][r][i];
+    }
+
+#pragma unroll
+    for (int k = 1; k < L; ++k) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = nt * 16 + lg + 4 * r;
+        Zs[n * QB + j] = dz[r];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Zs[(1 + i) * H * QB + n * QB + j] = zt[r][i];
+      }
+      __syncthreads();
+      d4_t acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = d4_t{0.0, 0.0, 0.0, 0.0};
+      const double* Wk = Wl + (k - 1) * H * HP + (nt * 16 + li) * HP + lg;
+#pragma unroll 4
+      for (int s = 0; s < H / 4; ++s) {
+        const double av = Wk[4 * s];
+        const int zb = (4 * s + lg) * QB + qt * 16 + li;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Zs[c * H * QB + zb], acc[c], 0, 0, 0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = nt * 16 + lg + 4 * r;
+        const double* wx = net + lay.Wx[k] + n * 3;
+        const double da = acc[0][r] + wx[0] * x[0] + wx[1] * x[1] + wx[2] * x[2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Jt[k][r][i] = acc[1 + i][r] + wx[i];
+        dz[r] = delta_softplus<double>(da, net[lay.a0 + k * H + n], net[lay.s0 + k * H + n],
+                                       net[lay.sb0 + k * H + n],
+                                       sS[k][r], sB[k][r]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) zt[r][i] = sS[k][r] * Jt[k][r][i];
+      }
+    }
+
+    // output layer partial sums over this lane's rows
+    double part[10];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) part[t] = 0.0;
+    double zbar[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = nt * 16 + lg + 4 * r;
+      const double wz = net[lay.wz + n];
+      part[0] += wz * dz[r];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
+      zbar[r] = wz;
+    }
+
+    if (a.with_hessian) {
+#pragma unroll
+      for (int k = L - 1; k >= 0; --k) {
+        double abar[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          abar[r] = zbar[r] * sS[k][r];
+          const double c2 = abar[r] * sB[k][r];
+          const double* Jr = Jt[k][r];
+          part[4] += c2 * Jr[0] * Jr[0];
+          part[5] += c2 * Jr[1] * Jr[1];
+          part[6] += c2 * Jr[2] * Jr[2];
+          part[7] += c2 * Jr[0] * Jr[1];
+          part[8] += c2 * Jr[0] * Jr[2];
+          part[9] += c2 * Jr[1] * Jr[2];
+        }
+        if (k > 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Zs[(nt * 16 + lg + 4 * r) * QB + j] = abar[r];
+          __syncthreads();
+          d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+          const double* Wt = Wl + (k - 1) * H * HP + lg * HP + nt * 16 + li;
+#pragma unroll 4
+          for (int s = 0; s < H / 4; ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wt[4 * s * HP],
+                                                        Zs[(4 * s + lg) * QB + qt * 16 + li], acc, 0,
+                                                        0, 0);
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < 4; ++r) zbar[r] = acc[r];
+        }
+      }
+    }
+
+    // reduce over the 4 row groups of the wave, then over the neuron tiles
+#pragma unroll
+    for (int t = 0; t < 10; ++t) {
+      part[t] += __shfl_xor(part[t], 16, 64);
+      part[t] += __shfl_xor(part[t], 32, 64);
+    }
+    __syncthreads();
+    if (lg == 0) {
+#pragma unroll
+      for (int t = 0; t < 10; ++t) red[(nt * QB + j) * 10 + t] = part[t];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < QB * 10; idx += blockDim.x) {
+      const int jj = idx / 10, t = idx % 10;
+      double v = 0.0;
+#pragma unroll
+      for (int u = 0; u < NT; ++u) v += red[(u * QB + jj) * 10 + t];
+      if (t == 0) v += net[lay.wx] * xs[jj * 3] + net[lay.wx + 1] * xs[jj * 3 + 1] + net[lay.wx + 2] * xs[jj * 3 + 2];
+      if (t >= 1 && t <= 3) v += net[lay.wx + t - 1];
+      if (q0 + jj < a.nq) a.jet[(q0 + jj) * 10 + t] = v;
+    }
+    __syncthreads();
+  }
+}
+
+template <int H, int L, int WAVES>
+static hipError_t launch_f64(const JetArgs& a, hipStream_t s, int num_cu) {
+  using C = JetCfg<H, L, WAVES>;
+  const int nbatch = (a.nq + C::QB - 1) / C::QB;
+  int per_cu = (160 * 1024) / C::LDS_BYTES;
+  if (per_cu < 1) per_cu = 1;
+  int grid = num_cu * per_cu;
+  if (grid > nbatch) grid = nbatch;
+  if (grid <= 0) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)jet_f64_kernel<H, L, WAVES>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((jet_f64_kernel<H, L, WAVES>), dim3(grid), dim3(WAVES * 64), C::LDS_BYTES, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_jet_f64(int H, const JetArgs& a, hipStream_t s, int num_cu) {
+  switch (H * 10 + a.L) {
+    case 161: return launch_f64<16, 1, 4>(a, s, num_cu);
+    case 162: return launch_f64<16, 2, 4>(a, s, num_cu);
+    case 163: return launch_f64<16, 3, 4>(a, s, num_cu);
+    case 321: return launch_f64<32, 1, 4>(a, s, num_cu);
+    case 322: return launch_f64<32, 2, 4>(a, s, num_cu);
+    case 323: return launch_f64<32, 3, 4>(a, s, num_cu);
+    case 641: return launch_f64<64, 1, 8>(a, s, num_cu);
+    case 642: return launch_f64<64, 2, 8>(a, s, num_cu);
+    case 643: return launch_f64<64, 3, 8>(a, s, num_cu);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace gedmg

@@ -1,0 +1,565 @@
+// Global Newton step of the monolithic scheme (Sec. 3.2: history updated in
+// every global iteration, tangent contributions of kappa included; each step
+// starts from the caller's predictor built on the last converged solution)
+// with a Jacobi-preconditioned Krylov solve per iteration.
+//
+// Sparse kernels are deterministic: fixed grids, per-block partial sums in a
+// fixed order, one-block final reductions; Krylov scalars stay on the device
+// and the host polls the residual norm only every few iterations.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "gedmg_internal.h"
+
+namespace gedmg {
+
+constexpr int kRedBlocks = 512;  // blocks of every reduction kernel
+constexpr int kThreads = 256;
+
+// Device scalar slots (doubles).
+enum Slot { S_RZ = 0, S_PAP, S_ALPHA, S_BETA, S_RR, S_BB, S_RHO, S_OMEGA, S_TT, S_TS, S_VR, S_RZNEW,
+            S_FLAG, S_NSLOTS = 16 };
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  return t;  // valid in thread 0
+}
+
+// ------------------------------------------------------------------ field kernels
+__global__ void set_dirichlet_kernel(double* u, double* phi, const int32_t* dof, const double* val,
+                                     int n, int dim, int n_nodes, uint8_t* mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int d = dof[i];
+  const int node = d / (dim + 1), c = d % (dim + 1);
+  if (c < dim)
+    u[(long)c * n_nodes + node] = val[i];
+  else
+    phi[node] = val[i];
+  mask[d] = 1;
+}
+
+__global__ void update_fields_kernel(double* u, double* phi, const double* delta, int dim, int n_nodes) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_nodes * (dim + 1)) return;
+  const int node = (int)(i / (dim + 1)), c = (int)(i % (dim + 1));
+  if (c < dim)
+    u[(long)c * n_nodes + node] += delta[i];
+  else
+    phi[node] += delta[i];
+}
+
+// b = -R with Dirichlet rows zeroed; partial sums of |b|^2 and non-finite flag.
+__global__ void rhs_kernel(const double* R, const uint8_t* mask, double* b, long n, double* part) {
+  __shared__ double sh[8];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double v = mask[i] ? 0.0 : -R[i];
+    b[i] = v;
+    s += v * v;
+  }
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Dirichlet rows / columns of K become identity rows / zero columns; the
+// inverse diagonal is stored for the Jacobi preconditioner.
+__global__ void mask_matrix_kernel(double* K, const int32_t* rowptr, const int32_t* col,
+                                   const uint8_t* mask, double* dinv, long nrows) {
+  const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const bool mr = mask[r];
+  double diag = 1.0;
+  for (int j = rowptr[r]; j < rowptr[r + 1]; ++j) {
+    const int c = col[j];
+    if (mr || mask[c]) K[j] = (c == r) ? 1.0 : 0.0;
+    if (c == r) diag = K[j];
+  }
+  dinv[r] = (diag != 0.0) ? 1.0 / diag : 1.0;
+}
+
+// y = K x (rows served by groups of G lanes) and partial sums of w . y.
+template <int G>
+__global__ void spmv_dot_kernel(const double* K, const int32_t* rowptr, const int32_t* col,
+                                const double* x, double* y, const double* w, long nrows, double* part) {
+  __shared__ double sh[8];
+  const int lane = threadIdx.x % G;
+  const long groups = (long)gridDim.x * (blockDim.x / G);
+  double acc_dot = 0.0;
+  for (long r = (long)blockIdx.x * (blockDim.x / G) + threadIdx.x / G; r < nrows; r += groups) {
+    double s = 0.0;
+    for (int j = rowptr[r] + lane; j < rowptr[r + 1]; j += G) s += K[j] * x[col[j]];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+    if (lane == 0) {
+      y[r] = s;
+      if (w) acc_dot += w[r] * s;
+    }
+  }
+  const double t = block_sum(acc_dot, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void dot2_kernel(const double* a, const double* b, const double* c, const double* d, long n,
+                            double* part) {
+  __shared__ double sh[8];
+  double s1 = 0.0, s2 = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    s1 += a[i] * b[i];
+    if (c) s2 += c[i] * d[i];
+  }
+  const double t1 = block_sum(s1, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t1;
+  const double t2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = t2;
+}
+
+// One-block reduction of kRedBlocks partials into scal[slot] (fixed order).
+__global__ void reduce_kernel(const double* part, double* scal, int slot, int slot2) {
+  __shared__ double sh[8];
+  double s = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) {
+    s += part[i];
+    if (slot2 >= 0) s2 += part[kRedBlocks + i];
+  }
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) scal[slot] = t;
+  if (slot2 >= 0) {
+    const double t2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) scal[slot2] = t2;
+  }
+}
+
+// ---- CG pieces
+__global__ void cg_alpha_kernel(double* scal) {
+  const double pap = scal[S_PAP];
+  if (!(pap > 0.0)) scal[S_FLAG] = 1.0;  // non-positive curvature
+  scal[S_ALPHA] = (pap > 0.0) ? scal[S_RZ] / pap : 0.0;
+}
+
+__global__ void cg_update_kernel(double* x, double* r, double* z, const double* p, const double* Ap,
+                                 const double* dinv, const double* scal, long n, double* part) {
+  __shared__ double sh[8];
+  const double alpha = scal[S_ALPHA];
+  double s1 = 0.0, s2 = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * Ap[i];
+    r[i] = ri;
+    const double zi = dinv[i] * ri;
+    z[i] = zi;
+    s1 += ri * zi;
+    s2 += ri * ri;
+  }
+  const double t1 = block_sum(s1, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t1;
+  const double t2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = t2;
+}
+
+__global__ void cg_beta_kernel(double* scal) {
+  const double rz = scal[S_RZ];
+  scal[S_BETA] = (rz != 0.0) ? scal[S_RZNEW] / rz : 0.0;
+  scal[S_RZ] = scal[S_RZNEW];
+}
+
+__global__ void cg_p_kernel(double* p, const double* z, const double* scal, long n) {
+  const double beta = scal[S_BETA];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void precond_kernel(double* z, const double* r, const double* dinv, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    z[i] = dinv[i] * r[i];
+}
+
+// ---- BiCGStab pieces (right Jacobi preconditioning)
+// p = r + beta (p - omega v), beta = (rho_new/rho) (alpha/omega)
+__global__ void bicg_p_kernel(double* p, const double* r, const double* v, const double* scal, long n) {
+  const double beta = scal[S_BETA], omega = scal[S_OMEGA];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+__global__ void bicg_scalars_kernel(double* scal, int stage) {
+  if (stage == 0) {  // after rho_new = r0 . r: beta
+    const double rho = scal[S_RHO], rn = scal[S_RZNEW];
+    const double om = scal[S_OMEGA], al = scal[S_ALPHA];
+    if (rho == 0.0 || om == 0.0) scal[S_FLAG] = 2.0;
+    scal[S_BETA] = (rho != 0.0 && om != 0.0) ? (rn / rho) * (al / om) : 0.0;
+    scal[S_RHO] = rn;
+  } else if (stage == 1) {  // after vr = r0 . v: alpha
+    const double vr = scal[S_VR];
+    if (vr == 0.0) scal[S_FLAG] = 2.0;
+    scal[S_ALPHA] = (vr != 0.0) ? scal[S_RHO] / vr : 0.0;
+  } else {  // after tt = t.t, ts = t.s: omega
+    const double tt = scal[S_TT];
+    scal[S_OMEGA] = (tt > 0.0) ? scal[S_TS] / tt : 0.0;
+    if (!(tt > 0.0)) scal[S_FLAG] = 2.0;
+  }
+}
+
+// s = r - alpha v (stored in r)
+__global__ void bicg_s_kernel(double* r, const double* v, const double* scal, long n) {
+  const double alpha = scal[S_ALPHA];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    r[i] -= alpha * v[i];
+}
+
+// x += alpha phat + omega shat; r = s - omega t; partial |r|^2
+__global__ void bicg_update_kernel(double* x, double* r, const double* ph, const double* sh_, const double* t,
+                                   const double* scal, long n, double* part) {
+  __shared__ double sh[8];
+  const double alpha = scal[S_ALPHA], omega = scal[S_OMEGA];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += alpha * ph[i] + omega * sh_[i];
+    const double ri = r[i] - omega * t[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  const double tt = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = tt;
+}
+
+__global__ void count_growth_kernel(const double* k1, const double* k0, long n, double* part) {
+  __shared__ double sh[8];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    s += (k1[i] > k0[i]) ? 1.0 : 0.0;
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void gather_sum_kernel(const double* R, const int32_t* idx, int n, double* part) {
+  __shared__ double sh[8];
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) s += R[idx[i]];
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+}  // namespace gedmg
+
+using namespace gedmg;
+
+namespace {
+
+#define GH(expr)                                                              \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      c->err = std::string(#expr) + ": " + hipGetErrorString(e_);             \
+      return GEDMG_E_HIP;                                                     \
+    }                                                                         \
+  } while (0)
+
+struct Work {
+  long ndof = 0, nnz = 0, nq = 0;
+  double *K = nullptr, *Kmp = nullptr, *R = nullptr, *Rmp = nullptr, *kt = nullptr, *ktmp = nullptr;
+  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *v = nullptr, *t = nullptr, *r0 = nullptr, *dinv = nullptr;
+  double *ub = nullptr, *phib = nullptr;
+  double *part = nullptr, *scal = nullptr, *hscal = nullptr;
+  uint8_t* mask = nullptr;
+};
+
+}  // namespace
+
+// The context keeps its Newton workspace behind an opaque pointer.
+namespace {
+struct WorkHolder {
+  gedmg_ctx* ctx;
+  Work w;
+};
+std::vector<WorkHolder*>& holders() {
+  static std::vector<WorkHolder*> h;
+  return h;
+}
+}  // namespace
+
+namespace gedmg {
+void release_newton_work(gedmg_ctx* c) {
+  auto& h = holders();
+  for (size_t i = 0; i < h.size(); ++i)
+    if (h[i]->ctx == c) {
+      Work& w = h[i]->w;
+      void* ptrs[] = {w.K, w.Kmp, w.R, w.Rmp, w.kt, w.ktmp, w.b, w.x, w.r, w.z, w.p, w.q,
+                      w.v, w.t, w.r0, w.dinv, w.ub, w.phib, w.part, w.scal, w.mask};
+      for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+      if (w.hscal) (void)hipHostFree(w.hscal);
+      delete h[i];
+      h.erase(h.begin() + i);
+      return;
+    }
+}
+}  // namespace gedmg
+
+namespace {
+
+int ensure_work(gedmg_ctx* c, Work** out) {
+  for (auto* h : holders())
+    if (h->ctx == c) {
+      *out = &h->w;
+      return GEDMG_OK;
+    }
+  auto* h = new WorkHolder{c, Work{}};
+  holders().push_back(h);
+  Work& w = h->w;
+  w.ndof = c->ndof;
+  w.nnz = c->nnz;
+  w.nq = (long)c->n_elems * c->nqp;
+  auto al = [&](double** p, long n) { return hipMalloc((void**)p, sizeof(double) * std::max(n, 1L)); };
+  if (al(&w.K, w.nnz) || al(&w.R, w.ndof) || al(&w.Rmp, w.ndof) || al(&w.kt, w.nq) ||
+      al(&w.ktmp, w.nq) || al(&w.b, w.ndof) || al(&w.x, w.ndof) || al(&w.r, w.ndof) ||
+      al(&w.z, w.ndof) || al(&w.p, w.ndof) || al(&w.q, w.ndof) || al(&w.v, w.ndof) ||
+      al(&w.t, w.ndof) || al(&w.r0, w.ndof) || al(&w.dinv, w.ndof) ||
+      al(&w.ub, (long)c->dim * c->n_nodes) || al(&w.phib, c->n_nodes) ||
+      al(&w.part, 2 * kRedBlocks) || al(&w.scal, S_NSLOTS) ||
+      hipMalloc((void**)&w.mask, std::max(w.ndof, 1L)) ||
+      hipHostMalloc((void**)&w.hscal, sizeof(double) * S_NSLOTS, 0)) {
+    c->err = "device allocation for the Newton workspace failed";
+    gedmg::release_newton_work(c);
+    return GEDMG_E_NOMEM;
+  }
+  *out = &w;
+  return GEDMG_OK;
+}
+
+int grid_for(long n) { return (int)std::min<long>(kRedBlocks, (n + kThreads - 1) / kThreads); }
+
+// y = K x, scal[slot] = w . y
+int spmv(gedmg_ctx* c, Work& w, const double* K, const double* x, double* y, const double* wv, int slot) {
+  const int G = c->dim == 3 ? 32 : 16;
+  if (G == 32)
+    hipLaunchKernelGGL((spmv_dot_kernel<32>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, K, c->drowptr,
+                       c->dcol, x, y, wv, w.ndof, w.part);
+  else
+    hipLaunchKernelGGL((spmv_dot_kernel<16>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, K, c->drowptr,
+                       c->dcol, x, y, wv, w.ndof, w.part);
+  GH(hipGetLastError());
+  if (slot >= 0) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, slot, -1);
+    GH(hipGetLastError());
+  }
+  return GEDMG_OK;
+}
+
+int dot2(gedmg_ctx* c, Work& w, const double* a, const double* b, const double* cc, const double* d,
+         int s1, int s2) {
+  hipLaunchKernelGGL(dot2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, a, b, cc, d, w.ndof, w.part);
+  GH(hipGetLastError());
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, s1, s2);
+  GH(hipGetLastError());
+  return GEDMG_OK;
+}
+
+int read_scalars(gedmg_ctx* c, Work& w) {
+  GH(hipMemcpyAsync(w.hscal, w.scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost, c->stream));
+  GH(hipStreamSynchronize(c->stream));
+  return GEDMG_OK;
+}
+
+// Solve K x = b (Jacobi-preconditioned CG; BiCGStab on non-positive curvature).
+// Returns iterations in *its.
+int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int* its) {
+  const long n = w.ndof;
+  const int gr = kRedBlocks;
+  int rc;
+  *its = 0;
+  GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
+  GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
+  GH(hipMemcpyAsync(w.r, w.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL(precond_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.z, w.r, w.dinv, n);
+  if ((rc = dot2(c, w, w.r, w.z, w.b, w.b, S_RZ, S_BB))) return rc;
+  GH(hipMemcpyAsync(w.p, w.z, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  if ((rc = read_scalars(c, w))) return rc;
+  const double bb = w.hscal[S_BB];
+  if (bb == 0.0) return GEDMG_OK;
+  if (!std::isfinite(bb)) { c->err = "non-finite right-hand side"; return GEDMG_E_NONFINITE; }
+  const double tol2 = rtol * rtol * bb;
+  const int check = 8;
+  bool use_bicg = false;
+  for (int it = 1; it <= max_it; ++it) {
+    if ((rc = spmv(c, w, K, w.p, w.q, w.p, S_PAP))) return rc;
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(1), 0, c->stream, w.scal);
+    hipLaunchKernelGGL(cg_update_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.x, w.r, w.z, w.p, w.q,
+                       w.dinv, w.scal, n, w.part);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_RZNEW, S_RR);
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(1), 0, c->stream, w.scal);
+    hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.z, w.scal, n);
+    GH(hipGetLastError());
+    *its = it;
+    if (it % check == 0 || it == max_it) {
+      if ((rc = read_scalars(c, w))) return rc;
+      if (w.hscal[S_FLAG] != 0.0) { use_bicg = true; break; }
+      if (!std::isfinite(w.hscal[S_RR])) { c->err = "non-finite Krylov residual"; return GEDMG_E_NONFINITE; }
+      if (w.hscal[S_RR] <= tol2) return GEDMG_OK;
+    }
+  }
+  if (!use_bicg) { c->err = "CG reached the iteration limit"; return GEDMG_E_LINSOLVE; }
+
+  // BiCGStab from x = 0 with right Jacobi preconditioning.
+  const int cg_its = *its;
+  GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
+  GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
+  GH(hipMemcpyAsync(w.r, w.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  GH(hipMemcpyAsync(w.r0, w.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  GH(hipMemsetAsync(w.p, 0, sizeof(double) * n, c->stream));
+  GH(hipMemsetAsync(w.v, 0, sizeof(double) * n, c->stream));
+  {
+    // rho = alpha = omega = 1
+    std::vector<double> init(S_NSLOTS, 0.0);
+    init[S_RHO] = init[S_ALPHA] = init[S_OMEGA] = 1.0;
+    std::copy(init.begin(), init.end(), w.hscal);
+    GH(hipMemcpyAsync(w.scal, w.hscal, sizeof(double) * S_NSLOTS, hipMemcpyHostToDevice, c->stream));
+    GH(hipStreamSynchronize(c->stream));
+  }
+  for (int it = 1; it <= max_it; ++it) {
+    if ((rc = dot2(c, w, w.r0, w.r, nullptr, nullptr, S_RZNEW, -1))) return rc;
+    hipLaunchKernelGGL(bicg_scalars_kernel, dim3(1), dim3(1), 0, c->stream, w.scal, 0);
+    hipLaunchKernelGGL(bicg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.v, w.scal, n);
+    hipLaunchKernelGGL(precond_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.z, w.p, w.dinv, n);  // phat
+    if ((rc = spmv(c, w, K, w.z, w.v, w.r0, S_VR))) return rc;                                            // v = K phat
+    hipLaunchKernelGGL(bicg_scalars_kernel, dim3(1), dim3(1), 0, c->stream, w.scal, 1);
+    hipLaunchKernelGGL(bicg_s_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.r, w.v, w.scal, n);     // s in r
+    hipLaunchKernelGGL(precond_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.q, w.r, w.dinv, n);  // shat
+    if ((rc = spmv(c, w, K, w.q, w.t, nullptr, -1))) return rc;                                         // t = K shat
+    if ((rc = dot2(c, w, w.t, w.t, w.t, w.r, S_TT, S_TS))) return rc;
+    hipLaunchKernelGGL(bicg_scalars_kernel, dim3(1), dim3(1), 0, c->stream, w.scal, 2);
+    hipLaunchKernelGGL(bicg_update_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.x, w.r, w.z, w.q, w.t,
+                       w.scal, n, w.part);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_RR, -1);
+    GH(hipGetLastError());
+    *its = cg_its + it;
+    if (it % check == 0 || it == max_it) {
+      if ((rc = read_scalars(c, w))) return rc;
+      if (!std::isfinite(w.hscal[S_RR])) { c->err = "non-finite Krylov residual"; return GEDMG_E_NONFINITE; }
+      if (w.hscal[S_RR] <= tol2) return GEDMG_OK;
+      if (w.hscal[S_FLAG] == 2.0) { c->err = "BiCGStab breakdown"; return GEDMG_E_LINSOLVE; }
+    }
+  }
+  c->err = "BiCGStab reached the iteration limit";
+  return GEDMG_E_LINSOLVE;
+}
+
+double sum_partials_host(gedmg_ctx* c, Work& w, int* rc) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_FLAG + 1, -1);
+  *rc = read_scalars(c, w);
+  return w.hscal[S_FLAG + 1];
+}
+
+}  // namespace
+
+extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const gedmg_solver_opts* opts_in,
+                                 int precision, double* u, double* phi, double* kappa,
+                                 const int32_t* reaction_dofs, int32_t n_reaction,
+                                 gedmg_newton_report* rep) {
+  if (!c) return GEDMG_E_ARG;
+  if (!bc || !u || !phi || !kappa || (bc->n > 0 && (!bc->dof || !bc->value)) || bc->n < 0 ||
+      (n_reaction > 0 && !reaction_dofs)) {
+    c->err = "null or inconsistent argument";
+    return GEDMG_E_ARG;
+  }
+  if (precision != GEDMG_FP64 && precision != GEDMG_BF16 && precision != GEDMG_FP16) {
+    c->err = "unknown precision";
+    return GEDMG_E_ARG;
+  }
+  gedmg_solver_opts o{25, 20000, 100, 1e-10, 0.0, 1e-12};
+  if (opts_in) o = *opts_in;
+  if (o.max_local <= 0 || o.max_newton < 0 || o.max_krylov <= 0) {
+    c->err = "solver limits must be positive";
+    return GEDMG_E_ARG;
+  }
+  c->max_local = o.max_local;
+  gedmg_newton_report local{};
+  gedmg_newton_report& r = rep ? *rep : local;
+  r = gedmg_newton_report{};
+  Work* wp = nullptr;
+  int rc = ensure_work(c, &wp);
+  if (rc) return rc;
+  Work& w = *wp;
+  const long n = w.ndof;
+  const int gr = kRedBlocks;
+  // backups for rollback
+  GH(hipMemcpyAsync(w.ub, u, sizeof(double) * c->dim * c->n_nodes, hipMemcpyDeviceToDevice, c->stream));
+  GH(hipMemcpyAsync(w.phib, phi, sizeof(double) * c->n_nodes, hipMemcpyDeviceToDevice, c->stream));
+  GH(hipMemsetAsync(w.mask, 0, n, c->stream));
+  if (bc->n > 0) {
+    hipLaunchKernelGGL(set_dirichlet_kernel, dim3((bc->n + 255) / 256), dim3(256), 0, c->stream, u, phi,
+                       bc->dof, bc->value, bc->n, c->dim, c->n_nodes, w.mask);
+    GH(hipGetLastError());
+  }
+  auto rollback = [&](int code) {
+    (void)hipMemcpyAsync(u, w.ub, sizeof(double) * c->dim * c->n_nodes, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(phi, w.phib, sizeof(double) * c->n_nodes, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    r.status = code;
+    return code;
+  };
+  const bool mixed = precision != GEDMG_FP64;
+  double res0 = -1.0;
+  for (int it = 0; it <= o.max_newton; ++it) {
+    // residual (FP64) and tangent (FP64 or mixed)
+    if (mixed) {
+      if ((rc = gedmg_assemble(c, u, phi, kappa, precision, w.Rmp, w.K, w.ktmp))) return rollback(rc);
+      if ((rc = gedmg_assemble(c, u, phi, kappa, GEDMG_FP64, w.R, nullptr, w.kt))) return rollback(rc);
+    } else {
+      if ((rc = gedmg_assemble(c, u, phi, kappa, GEDMG_FP64, w.R, w.K, w.kt))) return rollback(rc);
+    }
+    hipLaunchKernelGGL(rhs_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.R, w.mask, w.b, n, w.part);
+    GH(hipGetLastError());
+    const double res2 = sum_partials_host(c, w, &rc);
+    if (rc) return rollback(rc);
+    if ((rc = gedmg_status(c))) return rollback(rc);
+    const double res = std::sqrt(res2);
+    if (it < 32) r.res_norm[it] = res;
+    r.newton_iters = it;
+    if (!std::isfinite(res)) { c->err = "non-finite residual"; return rollback(GEDMG_E_NONFINITE); }
+    if (res0 < 0.0) res0 = res;
+    if (res <= std::max(o.newton_rtol * std::max(1.0, res0), o.newton_atol)) {
+      // converged: commit the history and report
+      GH(hipMemcpyAsync(w.ktmp, kappa, sizeof(double) * w.nq, hipMemcpyDeviceToDevice, c->stream));
+      GH(hipMemcpyAsync(kappa, w.kt, sizeof(double) * w.nq, hipMemcpyDeviceToDevice, c->stream));
+      hipLaunchKernelGGL(count_growth_kernel, dim3(gr), dim3(kThreads), 0, c->stream, kappa, w.ktmp, w.nq,
+                         w.part);
+      GH(hipGetLastError());
+      r.n_yielded_qp = (int)sum_partials_host(c, w, &rc);
+      if (rc) return rc;
+      if (n_reaction > 0) {
+        hipLaunchKernelGGL(gather_sum_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.R, reaction_dofs,
+                           n_reaction, w.part);
+        GH(hipGetLastError());
+        r.reaction = sum_partials_host(c, w, &rc);
+        if (rc) return rc;
+      }
+      r.status = GEDMG_OK;
+      return GEDMG_OK;
+    }
+    if (it == o.max_newton) break;
+    hipLaunchKernelGGL(mask_matrix_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, w.K, c->drowptr,
+                       c->dcol, w.mask, w.dinv, n);
+    GH(hipGetLastError());
+    int its = 0;
+    rc = krylov(c, w, w.K, o.max_krylov, o.krylov_rtol, &its);
+    r.krylov_iters_total += its;
+    if (rc) return rollback(rc);
+    hipLaunchKernelGGL(update_fields_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, u, phi, w.x,
+                       c->dim, c->n_nodes);
+    GH(hipGetLastError());
+  }
+  c->err = "Newton did not converge";
+  return rollback(GEDMG_E_NEWTON_NOCONV);
+}

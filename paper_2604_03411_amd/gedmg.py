@@ -1,0 +1,246 @@
+"""Python binding of the gedmg C ABI (include/gedmg.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library `libgedmg.so`.  Device arrays are torch tensors on the current HIP
+device; the torch current stream is handed to the library.  Importing this
+module without the built library raises immediately (there is no CPU
+fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgedmg.so")
+
+FP64, BF16, FP16 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "bf16": BF16, "fp16": FP16}
+
+ERRORS = {
+    -1: "GEDMG_E_ARG", -2: "GEDMG_E_SHAPE", -3: "GEDMG_E_NONFINITE", -4: "GEDMG_E_LOCAL_NOCONV",
+    -5: "GEDMG_E_NEWTON_NOCONV", -6: "GEDMG_E_LINSOLVE", -7: "GEDMG_E_HIP", -8: "GEDMG_E_NOMEM",
+    -9: "GEDMG_E_JNONPOS",
+}
+
+
+class GedmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int32), ("n_elems", C.c_int32),
+                ("X", C.POINTER(C.c_double)), ("conn", C.POINTER(C.c_int32))]
+
+
+class Material(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("mu_e", "lambda_e", "eta_d", "kappa_d", "c_d", "beta_d", "gamma_d")]
+
+
+class Icnn(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("width", C.c_int32), ("n_hidden", C.c_int32),
+                ("monotone_mask", C.c_int32), ("theta", C.POINTER(C.c_double))]
+
+
+class Dirichlet(C.Structure):
+    _fields_ = [("n", C.c_int32), ("dof", C.c_void_p), ("value", C.c_void_p)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("max_newton", C.c_int32), ("max_krylov", C.c_int32), ("max_local", C.c_int32),
+                ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("krylov_rtol", C.c_double)]
+
+
+class NewtonReport(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("krylov_iters_total", C.c_int32),
+                ("n_yielded_qp", C.c_int32), ("status", C.c_int32),
+                ("res_norm", C.c_double * 32), ("reaction", C.c_double)]
+
+
+class AdjointReport(C.Structure):
+    _fields_ = [("n_checkpoints", C.c_int32), ("recomputed_steps", C.c_int32),
+                ("newton_iters_total", C.c_int32), ("krylov_iters_total", C.c_int32),
+                ("t_forward_s", C.c_double), ("t_reverse_s", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"gedmg HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.gedmg_last_error.restype = C.c_char_p
+        L.gedmg_last_error.argtypes = [vp]
+        L.gedmg_create.argtypes = [C.POINTER(vp), C.POINTER(Mesh), C.POINTER(Material),
+                                   C.POINTER(Icnn), C.POINTER(Icnn), vp]
+        L.gedmg_destroy.argtypes = [vp]
+        L.gedmg_set_params.argtypes = [vp, C.POINTER(dp), C.POINTER(dp)]
+        L.gedmg_csr.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(vp), C.POINTER(vp)]
+        L.gedmg_assemble.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp, vp]
+        L.gedmg_status.argtypes = [vp]
+        L.gedmg_energy_jet.argtypes = [vp, vp, i64, C.c_int, vp]
+        if hasattr(L, "gedmg_newton_step"):
+            L.gedmg_newton_step.argtypes = [vp, C.POINTER(Dirichlet), C.POINTER(SolverOpts), C.c_int,
+                                            vp, vp, vp, vp, i32, C.POINTER(NewtonReport)]
+        if hasattr(L, "gedmg_adjoint"):
+            L.gedmg_adjoint.argtypes = [vp, i32, C.POINTER(Dirichlet), vp, i32, vp, i32,
+                                        C.POINTER(SolverOpts), C.POINTER(dp), C.POINTER(dp),
+                                        C.POINTER(dp), C.POINTER(AdjointReport)]
+        for name in ("gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
+                     "gedmg_assemble", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
+                     "gedmg_energy_jet"):
+            if hasattr(L, name):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("gedmg_last_error", "gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
+            "gedmg_assemble", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
+            "gedmg_energy_jet")
+
+
+def _hip():
+    return C.CDLL("libamdhip64.so")
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(None)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _f64(t, dev):
+    return torch.as_tensor(t, dtype=torch.float64, device=dev).contiguous()
+
+
+class Context:
+    """A gedmg context for one mesh, material and pair of networks."""
+
+    def __init__(self, mesh, material: dict, energy_spec, theta_e, yield_spec, theta_y,
+                 device="cuda"):
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.dev = dev
+        self.dim = int(mesh.dim)
+        self.n_nodes, self.n_elems = int(mesh.n_nodes), int(mesh.n_elems)
+        self.nqp = 4 if self.dim == 2 else 8
+        self.ndof = self.n_nodes * (self.dim + 1)
+        self._X = np.ascontiguousarray(mesh.X, dtype=np.float64)
+        self._conn = np.ascontiguousarray(mesh.conn, dtype=np.int32)
+        self._te = np.ascontiguousarray(theta_e, dtype=np.float64)
+        self._ty = np.ascontiguousarray(theta_y, dtype=np.float64)
+        m = Mesh(self.dim, self.n_nodes, self.n_elems,
+                 self._X.ctypes.data_as(C.POINTER(C.c_double)),
+                 self._conn.ctypes.data_as(C.POINTER(C.c_int32)))
+        mat = Material(*(float(material[k]) for k in
+                         ("mu_e", "lambda_e", "eta_d", "kappa_d", "c_d", "beta_d", "gamma_d")))
+        en = Icnn(energy_spec.n_in, energy_spec.width, energy_spec.n_hidden,
+                  energy_spec.monotone_mask, self._te.ctypes.data_as(C.POINTER(C.c_double)))
+        yl = Icnn(yield_spec.n_in, yield_spec.width, yield_spec.n_hidden,
+                  yield_spec.monotone_mask, self._ty.ctypes.data_as(C.POINTER(C.c_double)))
+        with torch.cuda.device(self.dev):
+            h = C.c_void_p()
+            rc = lib().gedmg_create(C.byref(h), C.byref(m), C.byref(mat), C.byref(en), C.byref(yl),
+                                    _stream())
+            self._h = h
+            if rc != 0:
+                msg = lib().gedmg_last_error(h).decode() if h.value else "create failed"
+                if h.value:
+                    lib().gedmg_destroy(h)
+                self._h = None
+                raise GedmgError(rc, msg)
+        n_rows, nnz = C.c_int64(), C.c_int64()
+        rp, cl = C.c_void_p(), C.c_void_p()
+        self._check(lib().gedmg_csr(self._h, C.byref(n_rows), C.byref(nnz), C.byref(rp), C.byref(cl)))
+        self.nnz = int(nnz.value)
+        self._rowptr_ptr, self._col_ptr = rp.value, cl.value
+
+    @classmethod
+    def from_case(cls, case, device="cuda"):
+        return cls(case.mesh, case.material, case.energy, case.theta_e, case.yield_, case.theta_y,
+                   device)
+
+    def _check(self, rc):
+        if rc != 0:
+            raise GedmgError(rc, lib().gedmg_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gedmg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- data
+    def csr(self):
+        """(rowptr, col) of the library's CSR pattern as int32 device tensors (copies)."""
+        rp = torch.empty(self.ndof + 1, dtype=torch.int32, device=self.dev)
+        cl = torch.empty(self.nnz, dtype=torch.int32, device=self.dev)
+        torch.cuda.current_stream().synchronize()
+        hip = _hip()
+        hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        for dst, src, n in ((rp, self._rowptr_ptr, rp.numel()), (cl, self._col_ptr, cl.numel())):
+            rc = hip.hipMemcpy(C.c_void_p(dst.data_ptr()), C.c_void_p(src), n * 4, 3)
+            if rc != 0:
+                raise GedmgError(-7, f"hipMemcpy failed ({rc})")
+        return rp, cl
+
+    def set_params(self, theta_e=None, theta_y=None):
+        te = None if theta_e is None else np.ascontiguousarray(theta_e, dtype=np.float64)
+        ty = None if theta_y is None else np.ascontiguousarray(theta_y, dtype=np.float64)
+        self._check(lib().gedmg_set_params(
+            self._h, None if te is None else te.ctypes.data_as(C.POINTER(C.c_double)),
+            None if ty is None else ty.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def fields(self, u, phi, kappa):
+        return _f64(u, self.dev), _f64(phi, self.dev), _f64(kappa, self.dev)
+
+    def assemble(self, u, phi, kappa, precision="fp64", tangent=True, out=None):
+        """Returns (R [ndof], K_vals [nnz] or None, kappa_trial [n_elems, nqp]) on the device."""
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if out is None:
+            R = torch.empty(self.ndof, dtype=torch.float64, device=self.dev)
+            K = torch.empty(self.nnz, dtype=torch.float64, device=self.dev) if tangent else None
+            kt = torch.empty(self.n_elems, self.nqp, dtype=torch.float64, device=self.dev)
+        else:
+            R, K, kt = out
+        for t, n in ((u, self.dim * self.n_nodes), (phi, self.n_nodes), (kappa, self.n_elems * self.nqp)):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n or t.device != self.dev:
+                raise GedmgError(-1, "fields must be contiguous float64 device tensors of the mesh size")
+        self._check(lib().gedmg_assemble(self._h, _dptr(u), _dptr(phi), _dptr(kappa), prec,
+                                         _dptr(R), _dptr(K), _dptr(kt)))
+        return R, K, kt
+
+    def energy_jet(self, x, precision="fp64"):
+        """Energy-network jet [n, 10] at inputs x [n, 3] (device tensors)."""
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        x = _f64(x, self.dev)
+        n = x.shape[0]
+        jet = torch.empty(n, 10, dtype=torch.float64, device=self.dev)
+        self._check(lib().gedmg_energy_jet(self._h, _dptr(x), n, prec, _dptr(jet)))
+        return jet
+
+    def status(self):
+        rc = lib().gedmg_status(self._h)
+        return rc
+
+    def check_status(self):
+        self._check(self.status())
