@@ -161,6 +161,15 @@ int gedmg_assemble(gedmg_ctx* ctx, const double* u, const double* phi, const dou
  * [n][10] = N(x) - N(0), dN/dx (3), d2N/dx2 (xx, yy, zz, xy, xz, yz). */
 int gedmg_energy_jet(gedmg_ctx* ctx, const double* x, int64_t n, int precision, double* jet);
 
+/* Per-phase timing of gedmg_assemble with HIP events recorded on the
+ * context's stream (for benchmarks).  enable != 0 starts recording and clears
+ * the totals.  gedmg_profile_read synchronises and returns, in ms summed over
+ * the assemblies since enabling: out[0] quadrature inputs, out[1] energy-
+ * network jets, out[2] element kernels (all colours), out[3] zero fills;
+ * *n_calls = assemblies timed.  out must hold 4 doubles (host). */
+int gedmg_profile(gedmg_ctx* ctx, int enable);
+int gedmg_profile_read(gedmg_ctx* ctx, double* out_ms, int32_t* n_calls);
+
 /* Synchronise the stream and return the sticky device status of the last
  * assemblies (GEDMG_OK, GEDMG_E_LOCAL_NOCONV or GEDMG_E_JNONPOS), then clear it. */
 int gedmg_status(gedmg_ctx* ctx);

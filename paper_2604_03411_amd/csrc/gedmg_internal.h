@@ -146,4 +146,8 @@ struct gedmg_ctx {
   double* djet = nullptr;              // [nq][10]
   int* dstatus = nullptr;
   int max_local = 100;                 // history-update iteration limit
+  // per-phase event profiling of gedmg_assemble
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;     // 5 events per timed assembly
+  int prof_calls = 0;
 };

@@ -167,6 +167,8 @@ int dalloc(gedmg_ctx* c, T** p, size_t n) {
 
 }  // namespace
 
+static void prof_clear(gedmg_ctx* c);
+
 extern "C" {
 
 const char* gedmg_last_error(const gedmg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -307,6 +309,7 @@ int gedmg_destroy(gedmg_ctx* ctx) {
   if (!ctx) return GEDMG_E_ARG;
   if (ctx->stream || ctx->dX) (void)hipStreamSynchronize(ctx->stream);
   release_newton_work(ctx);
+  prof_clear(ctx);
   free_all(ctx);
   delete ctx;
   return GEDMG_OK;
@@ -334,13 +337,25 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
     c->err = "unknown precision";
     return GEDMG_E_ARG;
   }
+  hipEvent_t ev[5] = {};
+  if (c->prof) {
+    for (int i = 0; i < 5; ++i) {
+      GEDMG_HIP(c, hipEventCreate(&ev[i]));
+      c->prof_ev.push_back(ev[i]);
+    }
+    c->prof_calls++;
+    GEDMG_HIP(c, hipEventRecord(ev[0], c->stream));
+  }
   GEDMG_HIP(c, hipMemsetAsync(R, 0, sizeof(double) * c->ndof, c->stream));
   if (K_vals) GEDMG_HIP(c, hipMemsetAsync(K_vals, 0, sizeof(double) * c->nnz, c->stream));
+  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[1], c->stream));
   KinArgs ka{c->dX, c->dconn, u, c->n_nodes, c->n_elems, c->dx, c->dstatus};
   GEDMG_HIP(c, launch_qp_inputs(c->dim, ka, c->stream));
+  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[2], c->stream));
   JetArgs ja{c->dx, c->djet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16,
              (int)((int64_t)c->n_elems * c->nqp), c->elay.L, K_vals ? 1 : 0};
   GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
+  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[3], c->stream));
   ElemArgs ea{};
   ea.X = c->dX; ea.conn = c->dconn; ea.perm = c->dperm; ea.blk = c->dblk; ea.rowstride = c->drowstride;
   ea.u = u; ea.phi = phi; ea.kappa_n = kappa_n; ea.jet = c->djet; ea.ynet = c->dynet;
@@ -353,6 +368,38 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
     ea.e_end = c->color_begin[k + 1];
     GEDMG_HIP(c, launch_element(c->dim, K_vals != nullptr, ea, c->ylay.total, c->stream, c->num_cu));
   }
+  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[4], c->stream));
+  return GEDMG_OK;
+}
+
+static void prof_clear(gedmg_ctx* c) {
+  for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+  c->prof_ev.clear();
+  c->prof_calls = 0;
+}
+
+int gedmg_profile(gedmg_ctx* c, int enable) {
+  if (!c) return GEDMG_E_ARG;
+  GEDMG_HIP(c, hipStreamSynchronize(c->stream));
+  prof_clear(c);
+  c->prof = enable != 0;
+  return GEDMG_OK;
+}
+
+int gedmg_profile_read(gedmg_ctx* c, double* out, int32_t* n_calls) {
+  if (!c || !out) return GEDMG_E_ARG;
+  GEDMG_HIP(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 4; ++i) out[i] = 0.0;
+  for (size_t b = 0; b + 4 < c->prof_ev.size() + 0 && b + 5 <= c->prof_ev.size(); b += 5) {
+    float ms;
+    const int map[4] = {1, 2, 3, 0};  // inputs, jets, elements, fills
+    for (int ph = 0; ph < 4; ++ph) {
+      const int i0 = map[ph];
+      GEDMG_HIP(c, hipEventElapsedTime(&ms, c->prof_ev[b + i0], c->prof_ev[b + i0 + 1]));
+      out[ph] += ms;
+    }
+  }
+  if (n_calls) *n_calls = c->prof_calls;
   return GEDMG_OK;
 }
 

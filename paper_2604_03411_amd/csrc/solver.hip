@@ -37,10 +37,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // ------------------------------------------------------------------ field kernels
 __global__ void set_dirichlet_kernel(double* u, double* phi, const int32_t* dof, const double* val,
-                                     int n, int dim, int n_nodes, uint8_t* mask) {
+                                     int n, int dim, int n_nodes, uint8_t* mask, double* scal) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int d = dof[i];
+  if (d < 0 || d >= n_nodes * (dim + 1)) {  // caller index out of range: flag, write nothing
+    scal[S_FLAG] = 3.0;
+    return;
+  }
   const int node = d / (dim + 1), c = d % (dim + 1);
   if (c < dim)
     u[(long)c * n_nodes + node] = val[i];
@@ -242,10 +246,13 @@ __global__ void count_growth_kernel(const double* k1, const double* k0, long n, 
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ void gather_sum_kernel(const double* R, const int32_t* idx, int n, double* part) {
+__global__ void gather_sum_kernel(const double* R, const int32_t* idx, int n, long ndof, double* part) {
   __shared__ double sh[8];
   double s = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) s += R[idx[i]];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int j = idx[i];
+    if (j >= 0 && j < ndof) s += R[j];
+  }
   const double t = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -497,10 +504,19 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
   GH(hipMemcpyAsync(w.ub, u, sizeof(double) * c->dim * c->n_nodes, hipMemcpyDeviceToDevice, c->stream));
   GH(hipMemcpyAsync(w.phib, phi, sizeof(double) * c->n_nodes, hipMemcpyDeviceToDevice, c->stream));
   GH(hipMemsetAsync(w.mask, 0, n, c->stream));
+  GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
   if (bc->n > 0) {
     hipLaunchKernelGGL(set_dirichlet_kernel, dim3((bc->n + 255) / 256), dim3(256), 0, c->stream, u, phi,
-                       bc->dof, bc->value, bc->n, c->dim, c->n_nodes, w.mask);
+                       bc->dof, bc->value, bc->n, c->dim, c->n_nodes, w.mask, w.scal);
     GH(hipGetLastError());
+    if ((rc = read_scalars(c, w))) return rc;
+    if (w.hscal[S_FLAG] != 0.0) {
+      c->err = "Dirichlet dof index out of range";
+      (void)hipMemcpyAsync(u, w.ub, sizeof(double) * c->dim * c->n_nodes, hipMemcpyDeviceToDevice, c->stream);
+      (void)hipMemcpyAsync(phi, w.phib, sizeof(double) * c->n_nodes, hipMemcpyDeviceToDevice, c->stream);
+      (void)hipStreamSynchronize(c->stream);
+      return GEDMG_E_ARG;
+    }
   }
   auto rollback = [&](int code) {
     (void)hipMemcpyAsync(u, w.ub, sizeof(double) * c->dim * c->n_nodes, hipMemcpyDeviceToDevice, c->stream);
@@ -540,7 +556,7 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
       if (rc) return rc;
       if (n_reaction > 0) {
         hipLaunchKernelGGL(gather_sum_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.R, reaction_dofs,
-                           n_reaction, w.part);
+                           n_reaction, n, w.part);
         GH(hipGetLastError());
         r.reaction = sum_partials_host(c, w, &rc);
         if (rc) return rc;

@@ -89,6 +89,8 @@ def lib():
         L.gedmg_assemble.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L.gedmg_status.argtypes = [vp]
         L.gedmg_energy_jet.argtypes = [vp, vp, i64, C.c_int, vp]
+        L.gedmg_profile.argtypes = [vp, C.c_int]
+        L.gedmg_profile_read.argtypes = [vp, C.POINTER(dp), C.POINTER(i32)]
         if hasattr(L, "gedmg_newton_step"):
             L.gedmg_newton_step.argtypes = [vp, C.POINTER(Dirichlet), C.POINTER(SolverOpts), C.c_int,
                                             vp, vp, vp, vp, i32, C.POINTER(NewtonReport)]
@@ -98,7 +100,7 @@ def lib():
                                         C.POINTER(dp), C.POINTER(AdjointReport)]
         for name in ("gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
                      "gedmg_assemble", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
-                     "gedmg_energy_jet"):
+                     "gedmg_energy_jet", "gedmg_profile", "gedmg_profile_read"):
             if hasattr(L, name):
                 getattr(L, name).restype = C.c_int
         _lib = L
@@ -107,7 +109,7 @@ def lib():
 
 EXPORTED = ("gedmg_last_error", "gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
             "gedmg_assemble", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
-            "gedmg_energy_jet")
+            "gedmg_energy_jet", "gedmg_profile", "gedmg_profile_read")
 
 
 def _hip():
@@ -237,6 +239,40 @@ class Context:
         jet = torch.empty(n, 10, dtype=torch.float64, device=self.dev)
         self._check(lib().gedmg_energy_jet(self._h, _dptr(x), n, prec, _dptr(jet)))
         return jet
+
+    def profile(self, enable=True):
+        self._check(lib().gedmg_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """Summed ms of (inputs, jets, elements, fills) and the number of timed assemblies."""
+        out = (C.c_double * 4)()
+        n = C.c_int32()
+        self._check(lib().gedmg_profile_read(self._h, out, C.byref(n)))
+        return dict(inputs=out[0], jets=out[1], elements=out[2], fills=out[3], calls=n.value)
+
+    def newton_step(self, u, phi, kappa, bc_dofs, bc_vals, precision="fp64", reaction_dofs=None,
+                    max_newton=25, max_krylov=20000, max_local=100, newton_rtol=1e-10,
+                    newton_atol=0.0, krylov_rtol=1e-12, raise_on_error=True):
+        """One monolithic load step in place on (u, phi, kappa); returns the report as a dict."""
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        dofs = torch.as_tensor(np.asarray(bc_dofs, dtype=np.int32), device=self.dev).contiguous()
+        vals = _f64(bc_vals, self.dev)
+        bc = Dirichlet(int(dofs.numel()), C.c_void_p(dofs.data_ptr()), C.c_void_p(vals.data_ptr()))
+        opts = SolverOpts(max_newton, max_krylov, max_local, newton_rtol, newton_atol, krylov_rtol)
+        rd = None
+        nr = 0
+        if reaction_dofs is not None:
+            rd = torch.as_tensor(np.asarray(reaction_dofs, dtype=np.int32), device=self.dev).contiguous()
+            nr = int(rd.numel())
+        rep = NewtonReport()
+        rc = lib().gedmg_newton_step(self._h, C.byref(bc), C.byref(opts), prec, _dptr(u), _dptr(phi),
+                                     _dptr(kappa), _dptr(rd), nr, C.byref(rep))
+        out = dict(status=rc, newton_iters=rep.newton_iters, krylov_iters=rep.krylov_iters_total,
+                   n_yielded_qp=rep.n_yielded_qp, reaction=rep.reaction,
+                   res_norm=list(rep.res_norm[: min(rep.newton_iters + 1, 32)]))
+        if rc != 0 and raise_on_error:
+            self._check(rc)
+        return out
 
     def status(self):
         rc = lib().gedmg_status(self._h)
