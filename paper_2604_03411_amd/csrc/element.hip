@@ -29,8 +29,7 @@ struct Tr<2> {
 template <int DIM>
 __device__ __forceinline__ int z3(int z) {
   if (DIM == 3) return z;
-  constexpr int m[7] = {0, 1, 3, 4, 9, 10, 11};
-  return m[z];
+  return z < 4 ? (z >> 1) * 3 + (z & 1) : z + 5;  // 0 1 3 4 | 9 10 11
 }
 
 // ------------------------------------------------------------------ kinematics
@@ -122,12 +121,14 @@ __global__ __launch_bounds__(256) void qp_inputs_kernel(KinArgs a) {
 // ------------------------------------------------------------------ yield network
 // N^_kappa(q) and its derivative, neurons split over the 8 lanes of a group.
 // `sc` is this group's LDS scratch of 2*H doubles.
-__device__ double yield_eval(const double* __restrict__ net, int H, int L, double yN0, int sub,
-                             double q, double* sc, double& dN) {
+template <int H>
+__device__ double yield_eval_h(const double* __restrict__ net, int L, double yN0, int sub, double q,
+                               double* sc, double& dN) {
   const NetLayout lay = make_layout_hd(1, H, L, 1);
   double pN = 0.0, pD = 0.0;
-  double z[4], zt[4];
-  const int per = H >> 3;
+  constexpr int per = H / 8;
+  double z[per], zt[per];
+#pragma unroll
   for (int j = 0; j < per; ++j) {
     const int n = sub + 8 * j;
     const double w = net[lay.W0 + n];
@@ -137,11 +138,13 @@ __device__ double yield_eval(const double* __restrict__ net, int H, int L, doubl
   }
   for (int k = 1; k < L; ++k) {
     wave_lds_sync();
+#pragma unroll
     for (int j = 0; j < per; ++j) {
       sc[sub + 8 * j] = z[j];
       sc[H + sub + 8 * j] = zt[j];
     }
     wave_lds_sync();
+#pragma unroll
     for (int j = 0; j < per; ++j) {
       const int n = sub + 8 * j;
       const double* Wz = net + lay.Wz[k] + n * H;
@@ -156,6 +159,7 @@ __device__ double yield_eval(const double* __restrict__ net, int H, int L, doubl
       zt[j] = s * acct;
     }
   }
+#pragma unroll
   for (int j = 0; j < per; ++j) {
     const double w = net[lay.wz + sub + 8 * j];
     pN = fma(w, z[j], pN);
@@ -168,26 +172,25 @@ __device__ double yield_eval(const double* __restrict__ net, int H, int L, doubl
   return pN + wx * q + net[lay.bout] - yN0;
 }
 
+
+
 // ------------------------------------------------------------------ per-qp state
+// Per-quadrature-point quantities the consistent tangent is built from.  The
+// 8 lanes of a group compute them redundantly; one copy per group lives in
+// LDS for the entry-parallel tangent (runtime-indexed, so not in registers).
 struct Qp {
   double F[9], A[9], Fi[9], Ci[9], C[9], b[9], Q[9];
   double x1F[9], x2F[9], psiF[9];
+  double Hx[9][3];   // sum_p d2N/dx_p dx_t * dx_p/dF_r
   double v[3], w[3];
   double J, I1, I2, Jm23, Jm53, Jm83, Jm4, Jm5, Jm6;
-  double Hn[6], m[3];
+  double m[3];
   double pv1, pv2;
   double f, fp, rhoF, kphi;
 };
 
-__device__ __forceinline__ double hn(const Qp& s, int a, int b) {
-  // packed symmetric Hessian (xx, yy, zz, xy, xz, yz)
-  if (a == b) return s.Hn[a];
-  const int lo = a < b ? a : b, hi = a < b ? b : a;
-  return (lo == 0) ? (hi == 1 ? s.Hn[3] : s.Hn[4]) : s.Hn[5];
-}
-
 // Entry (r, c) of the consistent tangent D = dPz/dz in 3-D z indices.
-__device__ double d_entry(const Qp& s, const Material& M, int r, int c) {
+__device__ double d_entry(const Qp& __restrict__ s, const Material& M, int r, int c) {
   if (r < 9 && c < 9) {
     const int i = r / 3, J = r % 3, k = c / 3, L = c % 3;
     const double dik = (i == k) ? 1.0 : 0.0, dJL = (J == L) ? 1.0 : 0.0;
@@ -203,13 +206,7 @@ __device__ double d_entry(const Qp& s, const Material& M, int r, int c) {
                         (4.0 / 3.0) * I22 * s.Jm5 * (s.Q[r] * s.A[c] + s.A[r] * s.Q[c]) +
                         (1.0 / 3.0) * I22 * s.Jm4 * I2FF + (20.0 / 9.0) * I23 * s.Jm6 * s.A[r] * s.A[c] -
                         (4.0 / 9.0) * I23 * s.Jm5 * JFF;
-    const double xr[3] = {s.x1F[r], s.x2F[r], s.A[r]};
-    const double xc[3] = {s.x1F[c], s.x2F[c], s.A[c]};
-    double hterm = 0.0;
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int t = 0; t < 3; ++t) hterm += hn(s, p, t) * xr[p] * xc[t];
+    const double hterm = s.Hx[r][0] * s.x1F[c] + s.Hx[r][1] * s.x2F[c] + s.Hx[r][2] * s.A[c];
     const double psiFF = M.mu * (hterm + s.m[0] * x1FF + s.m[1] * x2FF + s.m[2] * JFF) +
                          M.lam * (s.pv2 * s.A[r] * s.A[c] + s.pv1 * JFF);
     const double grad = M.c * (s.Fi[L * 3 + i] * s.w[k] * s.v[J] + s.w[i] * s.w[k] * s.Ci[J * 3 + L] +
@@ -236,7 +233,7 @@ __device__ double d_entry(const Qp& s, const Material& M, int r, int c) {
 }
 
 // ------------------------------------------------------------------ element kernel
-template <int DIM>
+template <int DIM, int YH>
 struct ElemLds {
   using T = Tr<DIM>;
   double G[8][T::NEN][3];  // grad N per qp
@@ -244,13 +241,14 @@ struct ElemLds {
   double Jw[8];
   double Pz[8][T::NZ];
   double D[8][T::NZ][T::NZ];
-  double ysc[8][64];       // yield-network scratch per group
+  double ysc[8][2 * YH];   // yield-network scratch per group
+  Qp qs[8];                // per-group state for the tangent entries
 };
 
-template <int DIM, bool TANGENT>
+template <int DIM, bool TANGENT, int YH>
 __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   using T = Tr<DIM>;
-  __shared__ ElemLds<DIM> S;
+  __shared__ ElemLds<DIM, YH> S;
   const int lane = threadIdx.x;
   const int g = lane >> 3, sub = lane & 7;
   const int es = (DIM == 3) ? 0 : (g >> 2);        // element slot of this group
@@ -314,13 +312,19 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   }
   if (sub == 0) S.Jw[g] = detJx;
 
-  Qp s;
+  // The group's state is built in LDS; the 8 lanes write identical values.
+  Qp& s = S.qs[g];
+  {
+    double Fr[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) s.F[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    for (int i = 0; i < 9; ++i) Fr[i] = (i % 4 == 0) ? 1.0 : 0.0;
 #pragma unroll
-  for (int i = 0; i < DIM; ++i)
+    for (int i = 0; i < DIM; ++i)
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) s.F[i * 3 + d] += group8_sum(un[i] * G[d]);
+      for (int d = 0; d < DIM; ++d) Fr[i * 3 + d] += group8_sum(un[i] * G[d]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s.F[i] = Fr[i];
+  }
   const double phi = group8_sum(phin * Nv);
   double gphi[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -393,8 +397,15 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   s.m[0] = jt[1];
   s.m[1] = jt[2];
   s.m[2] = jt[3] - a.n0;
+  if (TANGENT) {
+    const double h6[6] = {jt[4], jt[5], jt[6], jt[7], jt[8], jt[9]};
+    const double Hm[3][3] = {{h6[0], h6[3], h6[4]}, {h6[3], h6[1], h6[5]}, {h6[4], h6[5], h6[2]}};
 #pragma unroll
-  for (int i = 0; i < 6; ++i) s.Hn[i] = TANGENT ? jt[4 + i] : 0.0;
+    for (int r = 0; r < 9; ++r)
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        s.Hx[r][t] = Hm[0][t] * s.x1F[r] + Hm[1][t] * s.x2F[r] + Hm[2][t] * s.A[r];
+  }
   const double vol = s.J + iJ - 2.0;
   s.pv1 = 2.0 * vol * (1.0 - iJ * iJ);
   s.pv2 = 2.0 * (1.0 - iJ * iJ) * (1.0 - iJ * iJ) + 4.0 * vol * iJ * iJ * iJ;
@@ -413,12 +424,12 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     const double f0 = exp(-M.eta * fmax(kn - M.kd, 0.0));
     const double q0 = psi_e + gb * (phi - kn) / (M.eta * f0);
     double d0;
-    const double h0 = yield_eval(a.ynet, a.yH, a.yL, a.yN0, sub, q0, sc, d0) - kn;
+    const double h0 = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, q0, sc, d0) - kn;
     dNy = d0;
     yielded = valid && (h0 > 0.0);
     if (yielded) {
       double dtmp;
-      const double top = yield_eval(a.ynet, a.yH, a.yL, a.yN0, sub, psi_e, sc, dtmp);
+      const double top = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, psi_e, sc, dtmp);
       double lo = kn, hi = fmax(fmax(kn, phi), top);
       double k = kn, h = h0;
       bool conv = false;
@@ -439,7 +450,7 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
         k = kn1;
         const double fk1 = exp(-M.eta * fmax(k - M.kd, 0.0));
         const double qk = psi_e + gb * (phi - k) / (M.eta * fk1);
-        h = yield_eval(a.ynet, a.yH, a.yL, a.yN0, sub, qk, sc, dNy) - k;
+        h = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, qk, sc, dNy) - k;
         if (h > 0.0) lo = k; else hi = k;
         if (h == 0.0 || !(hi > lo)) { conv = true; break; }
       }
@@ -461,22 +472,20 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
 
   // ---------------- conjugates Pz = (P, dPsi/dphi, Y_vec) and the tangent
   if (sub == 0) {
-    double pz3[13];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < DIM; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) pz3[i * 3 + j] = s.f * s.psiF[i * 3 + j] - M.c * s.w[i] * s.v[j];
-    pz3[9] = M.beta * (phi - kap);
+      for (int j = 0; j < DIM; ++j) S.Pz[g][i * DIM + j] = s.f * s.psiF[i * 3 + j] - M.c * s.w[i] * s.v[j];
+    S.Pz[g][DIM * DIM] = M.beta * (phi - kap);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) pz3[10 + j] = M.c * s.v[j];
-#pragma unroll
-    for (int z = 0; z < T::NZ; ++z) S.Pz[g][z] = pz3[z3<DIM>(z)];
+    for (int j = 0; j < DIM; ++j) S.Pz[g][DIM * DIM + 1 + j] = M.c * s.v[j];
     if (valid) a.kappa_out[qg] = kap;
   }
   if (TANGENT) {
+    wave_lds_sync();
     for (int idx = sub; idx < T::NZ * T::NZ; idx += 8) {
       const int r = idx / T::NZ, c = idx % T::NZ;
-      S.D[g][r][c] = d_entry(s, M, z3<DIM>(r), z3<DIM>(c));
+      S.D[g][r][c] = d_entry(S.qs[g], M, z3<DIM>(r), z3<DIM>(c));
     }
   }
   __syncthreads();
@@ -588,21 +597,26 @@ hipError_t launch_qp_inputs(int dim, const KinArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int DIM, bool TAN>
+static void launch_elem_t(const ElemArgs& a, int blocks, hipStream_t s) {
+  if (a.yH == 16)
+    hipLaunchKernelGGL((element_kernel<DIM, TAN, 16>), dim3(blocks), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL((element_kernel<DIM, TAN, 32>), dim3(blocks), dim3(64), 0, s, a);
+}
+
 hipError_t launch_element(int dim, bool tangent, const ElemArgs& a, int, hipStream_t s, int) {
+  if (a.yH != 16 && a.yH != 32) return hipErrorInvalidValue;
   const int epw = dim == 3 ? 1 : 2;
   const int n = a.e_end - a.e_begin;
   const int blocks = (n + epw - 1) / epw;
   if (blocks == 0) return hipSuccess;
   if (dim == 3) {
-    if (tangent)
-      hipLaunchKernelGGL((element_kernel<3, true>), dim3(blocks), dim3(64), 0, s, a);
-    else
-      hipLaunchKernelGGL((element_kernel<3, false>), dim3(blocks), dim3(64), 0, s, a);
+    if (tangent) launch_elem_t<3, true>(a, blocks, s);
+    else launch_elem_t<3, false>(a, blocks, s);
   } else {
-    if (tangent)
-      hipLaunchKernelGGL((element_kernel<2, true>), dim3(blocks), dim3(64), 0, s, a);
-    else
-      hipLaunchKernelGGL((element_kernel<2, false>), dim3(blocks), dim3(64), 0, s, a);
+    if (tangent) launch_elem_t<2, true>(a, blocks, s);
+    else launch_elem_t<2, false>(a, blocks, s);
   }
   return hipGetLastError();
 }

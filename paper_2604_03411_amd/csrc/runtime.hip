@@ -114,7 +114,7 @@ int check_net(gedmg_ctx* c, const gedmg_icnn* n, int n_in, bool energy) {
   if (n->n_in != n_in) { c->err = "network input count not supported"; return GEDMG_E_SHAPE; }
   if (n->n_hidden < 1 || n->n_hidden > kMaxHidden) { c->err = "n_hidden must be 1..3"; return GEDMG_E_SHAPE; }
   const int H = n->width;
-  const bool ok = energy ? (H == 16 || H == 32 || H == 64) : (H == 8 || H == 16 || H == 24 || H == 32);
+  const bool ok = energy ? (H == 16 || H == 32 || H == 64) : (H == 16 || H == 32);
   if (!ok) { c->err = "network width not supported"; return GEDMG_E_SHAPE; }
   return GEDMG_OK;
 }
