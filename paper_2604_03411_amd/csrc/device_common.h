@@ -89,12 +89,23 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum over aligned groups of 8 lanes; every lane of the group gets the same
-// bits (the butterfly pairs commute).
+// Cross-lane move of a double within rows of the wavefront (DPP, no LDS).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over aligned groups of 8 lanes with DPP: swap neighbours (quad_perm
+// 1,0,3,2), swap pairs (quad_perm 2,3,0,1), then add the mirrored half-row
+// (the other quad of the 8).  Every lane of the group gets the same bits
+// (each addition pairs two equal-shape partial sums, which commute).
 __device__ __forceinline__ double group8_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
   return v;
 }
 

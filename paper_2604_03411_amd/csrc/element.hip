@@ -122,18 +122,21 @@ __global__ __launch_bounds__(256) void qp_inputs_kernel(KinArgs a) {
 // N^_kappa(q) and its derivative, neurons split over the 8 lanes of a group.
 // `sc` is this group's LDS scratch of 2*H doubles.
 template <int H>
-__device__ double yield_eval_h(const double* __restrict__ net, int L, double yN0, int sub, double q,
+__device__ __forceinline__ double yield_eval_h(const double* __restrict__ net, int L, double yN0, int sub, double q,
                                double* sc, double& dN) {
-  const NetLayout lay = make_layout_hd(1, H, L, 1);
+  // offsets of the packed single-input network (see make_layout_hd), in closed form
+  constexpr int oW0 = 0, ob0 = H;
+  const int stride = H * H + 2 * H;             // Wz, Wx, b of one hidden layer
+  const int owz = 2 * H + (L - 1) * stride;
   double pN = 0.0, pD = 0.0;
   constexpr int per = H / 8;
   double z[per], zt[per];
 #pragma unroll
   for (int j = 0; j < per; ++j) {
     const int n = sub + 8 * j;
-    const double w = net[lay.W0 + n];
+    const double w = net[oW0 + n];
     double s;
-    z[j] = softplus_d(w * q + net[lay.b0 + n], s);
+    z[j] = softplus_d(w * q + net[ob0 + n], s);
     zt[j] = s * w;
   }
   for (int k = 1; k < L; ++k) {
@@ -147,9 +150,10 @@ __device__ double yield_eval_h(const double* __restrict__ net, int L, double yN0
 #pragma unroll
     for (int j = 0; j < per; ++j) {
       const int n = sub + 8 * j;
-      const double* Wz = net + lay.Wz[k] + n * H;
-      double acc = net[lay.Wx[k] + n] * q + net[lay.b[k] + n];
-      double acct = net[lay.Wx[k] + n];
+      const int oWz = 2 * H + (k - 1) * stride, oWx = oWz + H * H, ob = oWx + H;
+      const double* Wz = net + oWz + n * H;
+      double acc = net[oWx + n] * q + net[ob + n];
+      double acct = net[oWx + n];
       for (int m = 0; m < H; ++m) {
         acc = fma(Wz[m], sc[m], acc);
         acct = fma(Wz[m], sc[H + m], acct);
@@ -161,75 +165,155 @@ __device__ double yield_eval_h(const double* __restrict__ net, int L, double yN0
   }
 #pragma unroll
   for (int j = 0; j < per; ++j) {
-    const double w = net[lay.wz + sub + 8 * j];
+    const double w = net[owz + sub + 8 * j];
     pN = fma(w, z[j], pN);
     pD = fma(w, zt[j], pD);
   }
   pN = group8_sum(pN);
   pD = group8_sum(pD);
-  const double wx = net[lay.wx];
+  const double wx = net[owz + H];
   dN = pD + wx;
-  return pN + wx * q + net[lay.bout] - yN0;
+  return pN + wx * q + net[owz + H + 1] - yN0;
 }
 
 
 
 // ------------------------------------------------------------------ per-qp state
-// Per-quadrature-point quantities the consistent tangent is built from.  The
-// 8 lanes of a group compute them redundantly; one copy per group lives in
-// LDS for the entry-parallel tangent (runtime-indexed, so not in registers).
+// Per-quadrature-point quantities the consistent tangent is built from (one
+// copy per 8-lane group in LDS; the lanes of the group write identical values).
+// Everything else the tangent needs (C, b, F^-1, C^-1 slices, dx/dF columns,
+// dpsi_e/dF) is rebuilt from these with a few multiply-adds per row.
 struct Qp {
-  double F[9], A[9], Fi[9], Ci[9], C[9], b[9], Q[9];
-  double x1F[9], x2F[9], psiF[9];
-  double Hx[9][3];   // sum_p d2N/dx_p dx_t * dx_p/dF_r
-  double v[3], w[3];
+  double F[9], A[9], Q[9];   // F, cof F = dJ/dF, dI2/dF = 2 (I1 F - F C)
+  double v[3], w[3];         // C^-1 grad phi, F C^-1 grad phi
+  double Hn[6];              // network Hessian (xx, yy, zz, xy, xz, yz)
   double J, I1, I2, Jm23, Jm53, Jm83, Jm4, Jm5, Jm6;
-  double m[3];
-  double pv1, pv2;
-  double f, fp, rhoF, kphi;
+  double m[3];               // dN/dx - n0 e3
+  double pv1, pv2;           // psi_vol', psi_vol''
+  double f, fp, rhoF, kphi;  // f_d, f_d', d kappa/dF = rhoF psi_e,F, d kappa/d phi
 };
 
-// Entry (r, c) of the consistent tangent D = dPz/dz in 3-D z indices.
-__device__ double d_entry(const Qp& __restrict__ s, const Material& M, int r, int c) {
-  if (r < 9 && c < 9) {
-    const int i = r / 3, J = r % 3, k = c / 3, L = c % 3;
-    const double dik = (i == k) ? 1.0 : 0.0, dJL = (J == L) ? 1.0 : 0.0;
-    const double JFF = (s.A[r] * s.A[c] - s.A[i * 3 + L] * s.A[k * 3 + J]) / s.J;
-    const double x1FF = 2.0 * s.Jm23 * dik * dJL -
-                        (4.0 / 3.0) * s.Jm53 * (s.F[r] * s.A[c] + s.A[r] * s.F[c]) +
-                        (10.0 / 9.0) * s.I1 * s.Jm83 * s.A[r] * s.A[c] -
-                        (2.0 / 3.0) * s.I1 * s.Jm53 * JFF;
-    const double I2FF = 2.0 * (2.0 * s.F[r] * s.F[c] + s.I1 * dik * dJL - dik * s.C[J * 3 + L] -
-                               s.F[i * 3 + L] * s.F[k * 3 + J] - s.b[i * 3 + k] * dJL);
-    const double I22 = s.I2 * s.I2, I23 = I22 * s.I2;
-    const double x2FF = (2.0 / 3.0) * s.I2 * s.Jm4 * s.Q[r] * s.Q[c] -
-                        (4.0 / 3.0) * I22 * s.Jm5 * (s.Q[r] * s.A[c] + s.A[r] * s.Q[c]) +
-                        (1.0 / 3.0) * I22 * s.Jm4 * I2FF + (20.0 / 9.0) * I23 * s.Jm6 * s.A[r] * s.A[c] -
-                        (4.0 / 9.0) * I23 * s.Jm5 * JFF;
-    const double hterm = s.Hx[r][0] * s.x1F[c] + s.Hx[r][1] * s.x2F[c] + s.Hx[r][2] * s.A[c];
-    const double psiFF = M.mu * (hterm + s.m[0] * x1FF + s.m[1] * x2FF + s.m[2] * JFF) +
-                         M.lam * (s.pv2 * s.A[r] * s.A[c] + s.pv1 * JFF);
-    const double grad = M.c * (s.Fi[L * 3 + i] * s.w[k] * s.v[J] + s.w[i] * s.w[k] * s.Ci[J * 3 + L] +
-                               s.w[i] * s.v[L] * s.Fi[J * 3 + k]);
-    return s.f * psiFF + grad + s.fp * s.psiF[r] * s.rhoF * s.psiF[c];
+// Row r (3-D z index) of the consistent tangent D = dPz/dz (Pz = (P, dPsi/dphi,
+// Y_vec), z = (F, phi, grad phi)), for the local columns of DIM:
+//   D_FF  = f_d psi_e,FF + grad-term_FF + f_d' rhoF psi_e,F (x) psi_e,F
+//   D_Fphi = f_d' psi_e,F kappa_phi,   D_Fg = -c_d (F^-T_iL v_J + w_i C^-1_JL)
+//   D_phiF = -beta_d rhoF psi_e,F,     D_phiphi = beta_d (1 - kappa_phi)
+//   D_gF = -c_d (F^-1_Jk v_L + w_k C^-1_LJ),  D_gg = c_d C^-1
+// with psi_e,FF = mu [x_F^T H x_F + m1 x1_FF + m2 x2_FF + m3 J_FF]
+//                + lambda [psi_vol'' A (x) A + psi_vol' J_FF]
+// written with the second derivatives of I1G, I2G and J (A = cof F):
+//   J_FF = (A_iJ A_kL - A_iL A_kJ)/J
+//   x1_FF = 2 J^-2/3 dd - 4/3 J^-5/3 (F A + A F) + 10/9 I1 J^-8/3 A A - 2/3 I1 J^-5/3 J_FF
+//   x2_FF = 2/3 I2 J^-4 Q Q - 4/3 I2^2 J^-5 (Q A + A Q) + 1/3 I2^2 J^-4 I2_FF
+//           + 20/9 I2^3 J^-6 A A - 4/9 I2^3 J^-5 J_FF
+//   I2_FF = 2 (2 F F + I1 dd - d_ik C_JL - F_iL F_kJ - b_ik d_JL)
+// and the gradient-energy term c_d (F^-T_Li w_k v_J + w_i w_k C^-1_JL + w_i v_L F^-1_Jk).
+template <int DIM>
+__device__ __forceinline__ void d_row(const Qp& __restrict__ s, const Material& M, int r, double* out) {
+  using T = Tr<DIM>;
+  double F[9], A[9], Q[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    F[t] = s.F[t];
+    A[t] = s.A[t];
+    Q[t] = s.Q[t];
   }
-  if (r < 9 && c == 9) return s.fp * s.psiF[r] * s.kphi;
+  const double iJ = 1.0 / s.J;
+  const double m0 = s.m[0], m1 = s.m[1], m2 = s.m[2];
+  const double I22 = s.I2 * s.I2, I23 = I22 * s.I2;
+  const double a1 = 2.0 * s.Jm23, b1 = -(2.0 / 3.0) * s.I1 * s.Jm53;      // x1_F = a1 F + b1 A
+  const double a2 = (1.0 / 3.0) * I22 * s.Jm4, b2 = -(4.0 / 9.0) * I23 * s.Jm5;  // x2_F = a2 Q + b2 A
+  auto psiF = [&](int c) {
+    const double x1 = a1 * F[c] + b1 * A[c], x2 = a2 * Q[c] + b2 * A[c];
+    return M.mu * (m0 * x1 + m1 * x2 + m2 * A[c]) + M.lam * s.pv1 * A[c];
+  };
   if (r < 9) {
-    const int i = r / 3, J = r % 3, L = c - 10;
-    return -M.c * (s.Fi[L * 3 + i] * s.v[J] + s.w[i] * s.Ci[J * 3 + L]);
+    const int i = r / 3, J = r % 3;
+    const double c_d1 = M.mu * m0 * a1;
+    const double c_FA = -M.mu * m0 * (4.0 / 3.0) * s.Jm53;
+    const double c_AA = M.mu * (m0 * (10.0 / 9.0) * s.I1 * s.Jm83 + m1 * (20.0 / 9.0) * I23 * s.Jm6) +
+                        M.lam * s.pv2;
+    const double c_J = M.mu * (-m0 * (2.0 / 3.0) * s.I1 * s.Jm53 - m1 * (4.0 / 9.0) * I23 * s.Jm5 + m2) +
+                       M.lam * s.pv1;
+    const double c_QQ = M.mu * m1 * (2.0 / 3.0) * s.I2 * s.Jm4;
+    const double c_QA = -M.mu * m1 * (4.0 / 3.0) * I22 * s.Jm5;
+    const double c_I2 = M.mu * m1 * (1.0 / 3.0) * I22 * s.Jm4;
+    const double Ar = A[r], Fr = F[r], Qr = Q[r], pr = psiF(r);
+    // H x_F for this row
+    const double x1r = a1 * Fr + b1 * Ar, x2r = a2 * Qr + b2 * Ar;
+    const double* Hn = s.Hn;
+    const double h0 = Hn[0] * x1r + Hn[3] * x2r + Hn[4] * Ar;
+    const double h1 = Hn[3] * x1r + Hn[1] * x2r + Hn[5] * Ar;
+    const double h2 = Hn[4] * x1r + Hn[5] * x2r + Hn[2] * Ar;
+    // row slices of C, b, F^-1 and C^-1
+    double CJ[3], bi[3], FiLi[3], FiJk[3], CiJ[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      CJ[t] = F[J] * F[t] + F[3 + J] * F[3 + t] + F[6 + J] * F[6 + t];
+      bi[t] = F[i * 3] * F[t * 3] + F[i * 3 + 1] * F[t * 3 + 1] + F[i * 3 + 2] * F[t * 3 + 2];
+      FiLi[t] = A[i * 3 + t] * iJ;   // F^-1_{t i}
+      FiJk[t] = A[t * 3 + J] * iJ;   // F^-1_{J t}
+      CiJ[t] = (A[J] * A[t] + A[3 + J] * A[3 + t] + A[6 + J] * A[6 + t]) * iJ * iJ;
+    }
+    const double wi = s.w[i], vJ = s.v[J];
+    const double rank1 = s.fp * s.rhoF * pr;
+#pragma unroll
+    for (int cz = 0; cz < T::NZ; ++cz) {
+      const int c = z3<DIM>(cz);
+      double v;
+      if (c < 9) {
+        const int k = c / 3, L = c % 3;
+        const double Ac = A[c], Fc = F[c], Qc = Q[c];
+        const double dik = (i == k) ? 1.0 : 0.0, dJL = (J == L) ? 1.0 : 0.0;
+        const double JFF = (Ar * Ac - A[i * 3 + L] * A[k * 3 + J]) * iJ;
+        const double I2FF = 2.0 * (2.0 * Fr * Fc + s.I1 * dik * dJL - dik * CJ[L] -
+                                   F[i * 3 + L] * F[k * 3 + J] - bi[k] * dJL);
+        const double x1c = a1 * Fc + b1 * Ac, x2c = a2 * Qc + b2 * Ac;
+        const double psiFF = M.mu * (h0 * x1c + h1 * x2c + h2 * Ac) + c_d1 * dik * dJL +
+                             c_FA * (Fr * Ac + Ar * Fc) + c_AA * Ar * Ac + c_J * JFF + c_QQ * Qr * Qc +
+                             c_QA * (Qr * Ac + Ar * Qc) + c_I2 * I2FF;
+        const double grad = M.c * (FiLi[L] * s.w[k] * vJ + wi * s.w[k] * CiJ[L] + wi * s.v[L] * FiJk[k]);
+        v = s.f * psiFF + grad + rank1 * psiF(c);
+      } else if (c == 9) {
+        v = s.fp * pr * s.kphi;
+      } else {
+        const int L = c - 10;
+        v = -M.c * (FiLi[L] * vJ + wi * CiJ[L]);
+      }
+      out[cz] = v;
+    }
+    return;
   }
   if (r == 9) {
-    if (c < 9) return -M.beta * s.rhoF * s.psiF[c];
-    if (c == 9) return M.beta * (1.0 - s.kphi);
-    return 0.0;
+    const double bk = -M.beta * s.rhoF;
+#pragma unroll
+    for (int cz = 0; cz < T::NZ; ++cz) {
+      const int c = z3<DIM>(cz);
+      out[cz] = (c < 9) ? bk * psiF(c) : (c == 9 ? M.beta * (1.0 - s.kphi) : 0.0);
+    }
+    return;
   }
   const int Jp = r - 10;
-  if (c < 9) {
-    const int k = c / 3, L = c % 3;
-    return -M.c * (s.Fi[Jp * 3 + k] * s.v[L] + s.w[k] * s.Ci[L * 3 + Jp]);
+  double FiJk[3], CiJ[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    FiJk[t] = A[t * 3 + Jp] * iJ;
+    CiJ[t] = (A[Jp] * A[t] + A[3 + Jp] * A[3 + t] + A[6 + Jp] * A[6 + t]) * iJ * iJ;
   }
-  if (c == 9) return 0.0;
-  return M.c * s.Ci[Jp * 3 + (c - 10)];
+#pragma unroll
+  for (int cz = 0; cz < T::NZ; ++cz) {
+    const int c = z3<DIM>(cz);
+    double v;
+    if (c < 9) {
+      const int k = c / 3, L = c % 3;
+      v = -M.c * (FiJk[k] * s.v[L] + s.w[k] * CiJ[L]);
+    } else if (c == 9) {
+      v = 0.0;
+    } else {
+      v = M.c * CiJ[c - 10];
+    }
+    out[cz] = v;
+  }
 }
 
 // ------------------------------------------------------------------ element kernel
@@ -242,7 +326,7 @@ struct ElemLds {
   double Pz[8][T::NZ];
   double D[8][T::NZ][T::NZ];
   double ysc[8][2 * YH];   // yield-network scratch per group
-  Qp qs[8];                // per-group state for the tangent entries
+  Qp qs[8];                // per-group state for the tangent rows
 };
 
 template <int DIM, bool TANGENT, int YH>
@@ -331,88 +415,91 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   for (int d = 0; d < DIM; ++d) gphi[d] = group8_sum(phin * G[d]);
 
   // ---------------- invariants and their first derivatives (all 8 lanes)
-  const double* F = s.F;
-  s.A[0] = F[4] * F[8] - F[5] * F[7];
-  s.A[1] = F[5] * F[6] - F[3] * F[8];
-  s.A[2] = F[3] * F[7] - F[4] * F[6];
-  s.A[3] = F[2] * F[7] - F[1] * F[8];
-  s.A[4] = F[0] * F[8] - F[2] * F[6];
-  s.A[5] = F[1] * F[6] - F[0] * F[7];
-  s.A[6] = F[1] * F[5] - F[2] * F[4];
-  s.A[7] = F[2] * F[3] - F[0] * F[5];
-  s.A[8] = F[0] * F[4] - F[1] * F[3];
-  s.J = F[0] * s.A[0] + F[1] * s.A[1] + F[2] * s.A[2];
-  if (valid && !(s.J > 0.0)) a.status[0] = GEDMG_E_JNONPOS;
-  const double iJ = 1.0 / s.J;
+  double F[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) F[t] = s.F[t];
+  double A[9];
+  A[0] = F[4] * F[8] - F[5] * F[7];
+  A[1] = F[5] * F[6] - F[3] * F[8];
+  A[2] = F[3] * F[7] - F[4] * F[6];
+  A[3] = F[2] * F[7] - F[1] * F[8];
+  A[4] = F[0] * F[8] - F[2] * F[6];
+  A[5] = F[1] * F[6] - F[0] * F[7];
+  A[6] = F[1] * F[5] - F[2] * F[4];
+  A[7] = F[2] * F[3] - F[0] * F[5];
+  A[8] = F[0] * F[4] - F[1] * F[3];
+  const double Jd = F[0] * A[0] + F[1] * A[1] + F[2] * A[2];
+  if (valid && !(Jd > 0.0)) a.status[0] = GEDMG_E_JNONPOS;
+  const double iJ = 1.0 / Jd;
+  double C[9], Q[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) s.Fi[i * 3 + j] = s.A[j * 3 + i] * iJ;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      s.C[i * 3 + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
-      s.b[i * 3 + j] = F[i * 3] * F[j * 3] + F[i * 3 + 1] * F[j * 3 + 1] + F[i * 3 + 2] * F[j * 3 + 2];
-      s.Ci[i * 3 + j] = s.Fi[i * 3] * s.Fi[j * 3] + s.Fi[i * 3 + 1] * s.Fi[j * 3 + 1] +
-                        s.Fi[i * 3 + 2] * s.Fi[j * 3 + 2];
-    }
-  s.I1 = s.C[0] + s.C[4] + s.C[8];
+    for (int j = 0; j < 3; ++j) C[i * 3 + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
+  const double I1 = C[0] + C[4] + C[8];
   double CC = 0.0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) CC += s.C[i] * s.C[i];
-  s.I2 = 0.5 * (s.I1 * s.I1 - CC);
-  // Q = dI2/dF = 2 (I1 F - F C)
+  for (int t = 0; t < 9; ++t) CC += C[t] * C[t];
+  const double I2 = 0.5 * (I1 * I1 - CC);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const double FC = F[i * 3] * s.C[j] + F[i * 3 + 1] * s.C[3 + j] + F[i * 3 + 2] * s.C[6 + j];
-      s.Q[i * 3 + j] = 2.0 * (s.I1 * F[i * 3 + j] - FC);
+      const double FC = F[i * 3] * C[j] + F[i * 3 + 1] * C[3 + j] + F[i * 3 + 2] * C[6 + j];
+      Q[i * 3 + j] = 2.0 * (I1 * F[i * 3 + j] - FC);
     }
-  const double cj = cbrt(s.J);
-  s.Jm23 = 1.0 / (cj * cj);
-  s.Jm53 = s.Jm23 * iJ;
-  s.Jm83 = s.Jm53 * iJ;
-  s.Jm4 = iJ * iJ * iJ * iJ;
-  s.Jm5 = s.Jm4 * iJ;
-  s.Jm6 = s.Jm5 * iJ;
-  const double x3 = s.J - 1.0;
-  const double I22 = s.I2 * s.I2;
+  const double cj = cbrt(Jd);
+  const double Jm23 = 1.0 / (cj * cj), Jm53 = Jm23 * iJ;
+  const double Jm4 = iJ * iJ * iJ * iJ, Jm5 = Jm4 * iJ;
+  const double x3 = Jd - 1.0;
+  const double I22 = I2 * I2;
+  // v = C^-1 grad phi (C^-1 = A^T A / J^2), w = F v
+  double v[3], w[3];
 #pragma unroll
-  for (int r = 0; r < 9; ++r) {
-    s.x1F[r] = 2.0 * s.Jm23 * F[r] - (2.0 / 3.0) * s.I1 * s.Jm53 * s.A[r];
-    s.x2F[r] = (1.0 / 3.0) * I22 * s.Jm4 * s.Q[r] - (4.0 / 9.0) * I22 * s.I2 * s.Jm5 * s.A[r];
+  for (int i = 0; i < 3; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      t += (A[i] * A[j] + A[3 + i] * A[3 + j] + A[6 + i] * A[6 + j]) * gphi[j];
+    v[i] = t * iJ * iJ;
   }
-  // v = C^-1 grad phi, w = F v
 #pragma unroll
-  for (int i = 0; i < 3; ++i) s.v[i] = s.Ci[i * 3] * gphi[0] + s.Ci[i * 3 + 1] * gphi[1] + s.Ci[i * 3 + 2] * gphi[2];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) s.w[i] = F[i * 3] * s.v[0] + F[i * 3 + 1] * s.v[1] + F[i * 3 + 2] * s.v[2];
+  for (int i = 0; i < 3; ++i) w[i] = F[i * 3] * v[0] + F[i * 3 + 1] * v[1] + F[i * 3 + 2] * v[2];
 
   // ---------------- energy from the network jet
   const long qg = (long)e * T::NQP + q;
   const double* jt = a.jet + qg * 10;
   const double dNx = jt[0];
-  s.m[0] = jt[1];
-  s.m[1] = jt[2];
-  s.m[2] = jt[3] - a.n0;
-  if (TANGENT) {
-    const double h6[6] = {jt[4], jt[5], jt[6], jt[7], jt[8], jt[9]};
-    const double Hm[3][3] = {{h6[0], h6[3], h6[4]}, {h6[3], h6[1], h6[5]}, {h6[4], h6[5], h6[2]}};
-#pragma unroll
-    for (int r = 0; r < 9; ++r)
-#pragma unroll
-      for (int t = 0; t < 3; ++t)
-        s.Hx[r][t] = Hm[0][t] * s.x1F[r] + Hm[1][t] * s.x2F[r] + Hm[2][t] * s.A[r];
-  }
-  const double vol = s.J + iJ - 2.0;
-  s.pv1 = 2.0 * vol * (1.0 - iJ * iJ);
-  s.pv2 = 2.0 * (1.0 - iJ * iJ) * (1.0 - iJ * iJ) + 4.0 * vol * iJ * iJ * iJ;
+  const double m0 = jt[1], m1 = jt[2], m2 = jt[3] - a.n0;
+  const double vol = Jd + iJ - 2.0;
+  const double pv1 = 2.0 * vol * (1.0 - iJ * iJ);
   const double psi_e = M.mu * (dNx - a.n0 * x3) + M.lam * vol * vol;
+  double psiF[9];
 #pragma unroll
-  for (int r = 0; r < 9; ++r)
-    s.psiF[r] = M.mu * (s.m[0] * s.x1F[r] + s.m[1] * s.x2F[r] + s.m[2] * s.A[r]) + M.lam * s.pv1 * s.A[r];
+  for (int r = 0; r < 9; ++r) {
+    const double x1 = 2.0 * Jm23 * F[r] - (2.0 / 3.0) * I1 * Jm53 * A[r];
+    const double x2 = (1.0 / 3.0) * I22 * Jm4 * Q[r] - (4.0 / 9.0) * I22 * I2 * Jm5 * A[r];
+    psiF[r] = M.mu * (m0 * x1 + m1 * x2 + m2 * A[r]) + M.lam * pv1 * A[r];
+  }
+  if (TANGENT) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      s.A[t] = A[t];
+      s.Q[t] = Q[t];
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      s.v[t] = v[t];
+      s.w[t] = w[t];
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) s.Hn[t] = jt[4 + t];
+    s.J = Jd; s.I1 = I1; s.I2 = I2;
+    s.Jm23 = Jm23; s.Jm53 = Jm53; s.Jm83 = Jm53 * iJ; s.Jm4 = Jm4; s.Jm5 = Jm5; s.Jm6 = Jm5 * iJ;
+    s.m[0] = m0; s.m[1] = m1; s.m[2] = m2;
+    s.pv1 = pv1;
+    s.pv2 = 2.0 * (1.0 - iJ * iJ) * (1.0 - iJ * iJ) + 4.0 * vol * iJ * iJ * iJ;
+  }
 
   // ---------------- local history update (Eq. dd_7), safeguarded Newton
   const double kn = valid ? a.kappa_n[qg] : 0.0;
@@ -428,10 +515,25 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     dNy = d0;
     yielded = valid && (h0 > 0.0);
     if (yielded) {
-      double dtmp;
-      const double top = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, psi_e, sc, dtmp);
+      // Bracket [lo, hi] with h(lo) > 0 >= h(hi).  At kappa = phi the driving
+      // force is psi_e, so one evaluation gives both h(phi) = N^(psi_e) - phi
+      // and the bracket top max(kappa_n, phi, N^(psi_e)) (on which q <= psi_e).
+      // With a large penalty the root sits just above phi: start there when
+      // the yield condition still holds at phi.
+      double dtop;
+      const double top = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, psi_e, sc, dtop);
       double lo = kn, hi = fmax(fmax(kn, phi), top);
       double k = kn, h = h0;
+      if (phi > kn) {
+        if (top - phi > 0.0) {
+          lo = phi;
+          k = phi;
+          h = top - phi;
+          dNy = dtop;
+        } else {
+          hi = phi;
+        }
+      }
       bool conv = false;
       for (int it = 0; it < a.max_local; ++it) {
         // Newton correction from the current iterate; the convergence test comes
@@ -458,16 +560,17 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
       kap = k;
     }
   }
-  s.f = exp(-M.eta * fmax(kap - M.kd, 0.0));
-  s.fp = (kap > M.kd) ? -M.eta * s.f : 0.0;
+  const double fkap = exp(-M.eta * fmax(kap - M.kd, 0.0));
+  const double fpkap = (kap > M.kd) ? -M.eta * fkap : 0.0;
+  double rhoF = 0.0, kphi = 0.0;
   if (yielded) {
-    const double dq = gb / (M.eta * s.f) * (-1.0 + ((kap > M.kd) ? M.eta * (phi - kap) : 0.0));
+    const double dq = gb / (M.eta * fkap) * (-1.0 + ((kap > M.kd) ? M.eta * (phi - kap) : 0.0));
     const double hk = dNy * dq - 1.0;
-    s.rhoF = -dNy / hk;
-    s.kphi = -dNy * gb / (M.eta * s.f) / hk;
-  } else {
-    s.rhoF = 0.0;
-    s.kphi = 0.0;
+    rhoF = -dNy / hk;
+    kphi = -dNy * gb / (M.eta * fkap) / hk;
+  }
+  if (TANGENT) {
+    s.f = fkap; s.fp = fpkap; s.rhoF = rhoF; s.kphi = kphi;
   }
 
   // ---------------- conjugates Pz = (P, dPsi/dphi, Y_vec) and the tangent
@@ -475,17 +578,27 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) S.Pz[g][i * DIM + j] = s.f * s.psiF[i * 3 + j] - M.c * s.w[i] * s.v[j];
+      for (int j = 0; j < DIM; ++j) S.Pz[g][i * DIM + j] = fkap * psiF[i * 3 + j] - M.c * w[i] * v[j];
     S.Pz[g][DIM * DIM] = M.beta * (phi - kap);
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) S.Pz[g][DIM * DIM + 1 + j] = M.c * s.v[j];
+    for (int j = 0; j < DIM; ++j) S.Pz[g][DIM * DIM + 1 + j] = M.c * v[j];
     if (valid) a.kappa_out[qg] = kap;
   }
   if (TANGENT) {
+    // rows of D per lane: 3-D -> F rows 0..7 on lanes 0..7, F row 8 on lane 0
+    // and the phi / grad-phi rows 9..12 on lanes 1..4; 2-D -> row sub (< 7)
     wave_lds_sync();
-    for (int idx = sub; idx < T::NZ * T::NZ; idx += 8) {
-      const int r = idx / T::NZ, c = idx % T::NZ;
-      S.D[g][r][c] = d_entry(S.qs[g], M, z3<DIM>(r), z3<DIM>(c));
+    double dr[T::NZ];
+    if (sub < T::NZ) {
+      d_row<DIM>(S.qs[g], M, z3<DIM>(sub), dr);
+#pragma unroll
+      for (int c = 0; c < T::NZ; ++c) S.D[g][sub][c] = dr[c];
+    }
+    if (DIM == 3 && sub <= 4) {
+      const int r1 = 8 + sub + (sub == 0 ? 0 : 0);
+      d_row<DIM>(S.qs[g], M, z3<DIM>(r1), dr);
+#pragma unroll
+      for (int c = 0; c < T::NZ; ++c) S.D[g][r1][c] = dr[c];
     }
   }
   __syncthreads();
@@ -500,7 +613,8 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
       const int ae = a.perm[slot_base + eslot];
       const int an = dl / T::ND, cc = dl % T::ND;
       double acc = 0.0;
-      for (int qq = 0; qq < T::NQP; ++qq) {
+#pragma unroll 1
+    for (int qq = 0; qq < T::NQP; ++qq) {
         const int gq = eslot * 4 + qq;
         double t;
         if (cc < DIM) {
@@ -534,6 +648,7 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     double Kacc[RPL];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) Kacc[t] = 0.0;
+#pragma unroll 1
     for (int qq = 0; qq < T::NQP; ++qq) {
       const int gq = eslot * 4 + qq;
       // B[:, col] nonzeros -> T = D B[:, col]
