@@ -118,8 +118,11 @@ typedef struct {
 } gedmg_newton_report;
 
 typedef struct {
-  int32_t n_checkpoints, recomputed_steps, newton_iters_total, krylov_iters_total;
-  double t_forward_s, t_reverse_s;
+  int32_t n_checkpoints;       /* states stored (one per segment) */
+  int32_t recomputed_steps;    /* load steps solved again from a checkpoint in the reverse sweep */
+  int32_t newton_iters_total;  /* forward and recomputed steps */
+  int32_t krylov_iters_total;  /* Newton solves and transposed adjoint solves */
+  double t_forward_s, t_recompute_s, t_reverse_s;  /* wall time of the three phases */
 } gedmg_adjoint_report;
 
 /* Message for the last failure on this context (never NULL). */
@@ -187,6 +190,45 @@ int gedmg_newton_step(gedmg_ctx* ctx, const gedmg_dirichlet* bc, const gedmg_sol
                       int precision, double* u, double* phi, double* kappa,
                       const int32_t* reaction_dofs, int32_t n_reaction,
                       gedmg_newton_report* report);
+
+/* Gradient of the load-path loss L = sum_n (r_n - t_n)^2, r_n the reaction of
+ * step n, with respect to the raw parameters of both networks (the paper
+ * motivates differentiating through the solver for design and inverse
+ * problems, Sec. 5; the residual and history update are those of Secs. 3.1-3.2).
+ *
+ * Runs the n_steps load steps of gedmg_newton_step (FP64) from the state
+ * (u, phi, kappa) passed in, then the discrete adjoint backwards over the
+ * steps: per step a transposed Krylov solve K_T^T lambda = d(ell_n + abar .
+ * kappa_n)/dU on the free dofs, the vector-Jacobian products of the residual
+ * and of the history update with respect to the parameters, and the history
+ * adjoint abar_{n-1}.  States are stored only at the start of every segment of
+ * checkpoint_every steps and recomputed segment by segment (checkpoint_every
+ * <= 0 or >= n_steps: one segment, nothing recomputed).  The recompute is
+ * bitwise identical to the forward pass, so the gradient does not depend on
+ * checkpoint_every.
+ *
+ *   bc_per_step   host array [n_steps] of Dirichlet sets (device dof/value)
+ *   predictor_du  device [n_steps][dim][n_nodes] displacement increments added
+ *                 to u before each step (the predictor), or NULL
+ *   reaction_dofs device [n_reaction], distinct, prescribed in every step
+ *   targets       device [n_steps]
+ *   opts          Newton / Krylov options of every solve (NULL: defaults)
+ *   u, phi, kappa device state: in, the start of the path; out, its end
+ *   loss          host scalar
+ *   grad_energy   host [n_params(energy)], raw order
+ *   grad_yield    host [n_params(yield)], raw order
+ *   report        host, may be NULL
+ * The output biases cancel in N - N(0): their gradients are exactly zero.
+ * Synchronises the stream.  Device memory: about (n_steps / checkpoint_every
+ * + checkpoint_every) states, two CSR value arrays and per-point network
+ * activations, allocated per call.  Errors: those of gedmg_newton_step
+ * (then the state is unspecified), GEDMG_E_ARG for bad reaction dofs,
+ * GEDMG_E_SHAPE for yield widths above 32. */
+int gedmg_adjoint(gedmg_ctx* ctx, int32_t n_steps, const gedmg_dirichlet* bc_per_step,
+                  const double* predictor_du, const int32_t* reaction_dofs, int32_t n_reaction,
+                  const double* targets, int32_t checkpoint_every, const gedmg_solver_opts* opts,
+                  double* u, double* phi, double* kappa, double* loss, double* grad_energy,
+                  double* grad_yield, gedmg_adjoint_report* report);
 
 #ifdef __cplusplus
 }

@@ -535,6 +535,11 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
         }
       }
       bool conv = false;
+      // Step sizes of the last two iterations: a Newton step longer than half
+      // the step before the last one is replaced by bisection, so the bracket
+      // at least halves every second iteration even when h is dominated by
+      // rounding near the root (there the Newton corrections are noise).
+      double step1 = hi - lo, step2 = hi - lo;
       for (int it = 0; it < a.max_local; ++it) {
         // Newton correction from the current iterate; the convergence test comes
         // before the bracket safeguard so that a root reached on the bracket's
@@ -542,19 +547,26 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
         const double fk = exp(-M.eta * fmax(k - M.kd, 0.0));
         const double dq = gb / (M.eta * fk) * (-1.0 + ((k > M.kd) ? M.eta * (phi - k) : 0.0));
         const double dk = -h / (dNy * dq - 1.0);
-        if (fabs(dk) <= 1e-15 * fmax(1.0, fabs(k))) {
+        const double tol = 1e-15 * fmax(1.0, fabs(k));
+        if (fabs(dk) <= tol) {
           k = fmin(fmax(k + dk, lo), hi);
           conv = true;
           break;
         }
         double kn1 = k + dk;
-        if (!(kn1 > lo && kn1 < hi)) kn1 = 0.5 * (lo + hi);
+        step2 = step1;
+        if (!(kn1 > lo && kn1 < hi) || 2.0 * fabs(dk) > step2) {
+          kn1 = 0.5 * (lo + hi);
+          step1 = 0.5 * (hi - lo);
+        } else {
+          step1 = fabs(dk);
+        }
         k = kn1;
         const double fk1 = exp(-M.eta * fmax(k - M.kd, 0.0));
         const double qk = psi_e + gb * (phi - k) / (M.eta * fk1);
         h = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, qk, sc, dNy) - k;
         if (h > 0.0) lo = k; else hi = k;
-        if (h == 0.0 || !(hi > lo)) { conv = true; break; }
+        if (h == 0.0 || !(hi - lo > tol)) { conv = true; break; }
       }
       if (!conv) a.status[0] = GEDMG_E_LOCAL_NOCONV;
       kap = k;

@@ -116,6 +116,16 @@ hipError_t launch_element(int dim, bool tangent, const ElemArgs& a, int ynet_dou
                           hipStream_t s, int num_cu);
 void release_newton_work(gedmg_ctx* c);
 
+// Sparse helpers of the Newton driver, reused by the adjoint.
+// y = K x over the context's CSR pattern.
+int solver_spmv(gedmg_ctx* c, const double* K, const double* x, double* y);
+// Solve A x = rhs on the free dofs: A (CSR values) is masked in place (rows and
+// columns of bc->dof become identity rows / zero columns), prescribed entries of
+// rhs are ignored and x is zero there.  `refine` passes of iterative refinement
+// on the true residual follow the first Krylov solve.
+int solver_solve_free(gedmg_ctx* c, double* A, const gedmg_dirichlet* bc, const double* rhs, double* x,
+                      int max_it, double rtol, int refine, int* its);
+
 }  // namespace gedmg
 
 // The opaque context.

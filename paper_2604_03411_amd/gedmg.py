@@ -66,7 +66,7 @@ class NewtonReport(C.Structure):
 class AdjointReport(C.Structure):
     _fields_ = [("n_checkpoints", C.c_int32), ("recomputed_steps", C.c_int32),
                 ("newton_iters_total", C.c_int32), ("krylov_iters_total", C.c_int32),
-                ("t_forward_s", C.c_double), ("t_reverse_s", C.c_double)]
+                ("t_forward_s", C.c_double), ("t_recompute_s", C.c_double), ("t_reverse_s", C.c_double)]
 
 
 _lib = None
@@ -95,8 +95,8 @@ def lib():
             L.gedmg_newton_step.argtypes = [vp, C.POINTER(Dirichlet), C.POINTER(SolverOpts), C.c_int,
                                             vp, vp, vp, vp, i32, C.POINTER(NewtonReport)]
         if hasattr(L, "gedmg_adjoint"):
-            L.gedmg_adjoint.argtypes = [vp, i32, C.POINTER(Dirichlet), vp, i32, vp, i32,
-                                        C.POINTER(SolverOpts), C.POINTER(dp), C.POINTER(dp),
+            L.gedmg_adjoint.argtypes = [vp, i32, C.POINTER(Dirichlet), vp, vp, i32, vp, i32,
+                                        C.POINTER(SolverOpts), vp, vp, vp, C.POINTER(dp), C.POINTER(dp),
                                         C.POINTER(dp), C.POINTER(AdjointReport)]
         for name in ("gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
                      "gedmg_assemble", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
@@ -274,9 +274,87 @@ class Context:
             self._check(rc)
         return out
 
+    def adjoint(self, path, checkpoint_every=5):
+        """Loss and raw-parameter gradients of a load path (see LoadPath).
+
+        Returns (loss, grad_energy, grad_yield, report dict); the path's
+        initial state is left untouched (the solve runs on copies)."""
+        n = path.n_steps
+        dv = self.dev
+        keep = []
+        bcs = (Dirichlet * n)()
+        for i, (bd, bv) in enumerate(path.bcs):
+            d = torch.as_tensor(np.asarray(bd, dtype=np.int32), device=dv).contiguous()
+            v = _f64(bv, dv)
+            keep += [d, v]
+            bcs[i] = Dirichlet(int(d.numel()), C.c_void_p(d.data_ptr()), C.c_void_p(v.data_ptr()))
+        pred = None if path.predictor_du is None else _f64(path.predictor_du, dv)
+        if pred is not None and pred.numel() != n * self.dim * self.n_nodes:
+            raise GedmgError(-1, "predictor_du must hold n_steps x dim x n_nodes values")
+        rd = torch.as_tensor(np.asarray(path.reaction_dofs, dtype=np.int32), device=dv).contiguous()
+        tg = _f64(path.targets, dv)
+        if tg.numel() != n:
+            raise GedmgError(-1, "one target per load step")
+        u, phi, kap = (_f64(t, dv).clone() for t in (path.u0, path.phi0, path.kappa0))
+        o = path.opts
+        opts = SolverOpts(o.get("max_newton", 25), o.get("max_krylov", 20000), o.get("max_local", 100),
+                          o.get("newton_rtol", 1e-10), o.get("newton_atol", 0.0), o.get("krylov_rtol", 1e-12))
+        ge = np.zeros(self._te.size)
+        gy = np.zeros(self._ty.size)
+        loss = C.c_double()
+        rep = AdjointReport()
+        self._check(lib().gedmg_adjoint(
+            self._h, n, bcs, _dptr(pred), _dptr(rd), int(rd.numel()), _dptr(tg), int(checkpoint_every),
+            C.byref(opts), _dptr(u), _dptr(phi), _dptr(kap), C.byref(loss),
+            ge.ctypes.data_as(C.POINTER(C.c_double)), gy.ctypes.data_as(C.POINTER(C.c_double)),
+            C.byref(rep)))
+        report = {k: getattr(rep, k) for k, _ in AdjointReport._fields_}
+        report["state"] = (u, phi, kap)
+        return loss.value, ge, gy, report
+
     def status(self):
         rc = lib().gedmg_status(self._h)
         return rc
 
     def check_status(self):
         self._check(self.status())
+
+
+class LoadPath:
+    """A displacement-controlled load path: initial state, per-step Dirichlet
+    sets (dofs, values), per-step predictor increments [n_steps][dim][n_nodes]
+    (or None), reaction dofs, per-step reaction targets and solver options
+    (keys of gedmg_solver_opts)."""
+
+    def __init__(self, u0, phi0, kappa0, bcs, reaction_dofs, targets, predictor_du=None, **opts):
+        self.u0, self.phi0, self.kappa0 = u0, phi0, kappa0
+        self.bcs = list(bcs)
+        self.n_steps = len(self.bcs)
+        self.reaction_dofs = reaction_dofs
+        self.targets = np.asarray(targets, dtype=np.float64)
+        self.predictor_du = predictor_du
+        self.opts = opts
+
+
+class LoadPathLoss(torch.autograd.Function):
+    """loss = sum_n (reaction_n - target_n)^2 over a load path as a function of
+    the raw network parameters; the gradient comes from gedmg_adjoint, which
+    computes it together with the loss in the forward call."""
+
+    @staticmethod
+    def forward(fctx, theta_e, theta_y, context, path, checkpoint_every=5):
+        context.set_params(theta_e.detach().cpu().numpy(), theta_y.detach().cpu().numpy())
+        loss, ge, gy, rep = context.adjoint(path, checkpoint_every)
+        fctx.save_for_backward(torch.as_tensor(ge, dtype=theta_e.dtype, device=theta_e.device),
+                               torch.as_tensor(gy, dtype=theta_y.dtype, device=theta_y.device))
+        fctx.report = rep
+        return torch.tensor(loss, dtype=theta_e.dtype, device=theta_e.device)
+
+    @staticmethod
+    def backward(fctx, g):
+        ge, gy = fctx.saved_tensors
+        return g * ge, g * gy, None, None, None
+
+
+def load_path_loss(context, theta_e, theta_y, path, checkpoint_every=5):
+    return LoadPathLoss.apply(theta_e, theta_y, context, path, checkpoint_every)
