@@ -1,25 +1,34 @@
 #!/usr/bin/env python
 """Throughput of the gradient-enhanced damage hot path on one MI355X.
 
-Workload: the 64x64x64 Hex8 unit cube (262 144 elements, 2 097 152
-quadrature points, 1 098 500 dofs, 115 024 912 CSR entries) with the
-3 -> 64 -> 64 -> 64 -> 1 energy network and the 1 -> 16 -> 1 yield network,
-seeded heterogeneous stretch field, phi ~ U(0, 0.2), kappa ~ U(0, 0.1).
-A step is one FP64 residual + consistent-tangent assembly: quadrature inputs,
-energy-network jets, history update, element integration and coloured CSR
-scatter.  The metric is quadrature-point residual+tangent evaluations per
-second with every input resident in HBM.
+Workload (headline): the 64x64x64 Hex8 unit cube (262 144 elements,
+2 097 152 quadrature points, 1 098 500 dofs, 115 024 912 CSR entries) with
+the 3 -> 64 -> 64 -> 64 -> 1 energy network and the 1 -> 16 -> 1 yield
+network, seeded heterogeneous stretch field, phi ~ U(0, 0.2),
+kappa ~ U(0, 0.1).  A step is one FP64 residual + consistent-tangent
+assembly: quadrature inputs, energy-network jets, history update, element
+integration and coloured CSR scatter.  The metric is quadrature-point
+residual+tangent evaluations per second with every input resident in HBM.
 
-Also reported: the mixed-precision (BF16 matrix-core) assembly of the same
-workload when available, the per-phase split measured with HIP events on the
-library's stream, the roofline of the dominant kernel, and the FP64 oracle
-timed on the host cores over a bounded sample of the same workload.
+Also reported on the same line:
+  - the mixed-precision (BF16 and FP16 matrix-core) assembly of the same
+    workload, with its error against the FP64 path on the residual
+    (integrated stress), the tangent, and the converged displacement of a
+    short notched-plate load path solved with the mixed tangent and the FP64
+    residual;
+  - the load-path adjoint on the 128x128 Q4 workload (20 steps, checkpoint
+    every 5 steps), in seconds per load step, with its phases;
+  - the per-phase split measured with HIP events on the library's stream, the
+    roofline of the dominant kernel, and the FP64 oracle timed on the host
+    cores over a bounded sample of the headline workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-mixed] [--no-adjoint] [--copy-probe]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,8 +38,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
-PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 / FP16 matrix
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_energy_jet_fp64_hex8_64cube.txt")
+JET_SOURCE = os.path.join(ROOT, "paper_2604_03411_amd", "csrc", "icnn_jet.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def jet_flops_per_qp(width, n_hidden, with_hessian=True):
@@ -62,6 +77,89 @@ def time_assembly(ctx, fields, out, precision, steps, warmup, torch):
     return ms, prof
 
 
+def per_call(prof, key):
+    return prof[key] / max(prof["calls"], 1)
+
+
+def rel_err(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
+def mixed_newton_error(G, W, torch, precision):
+    """Converged-state error of a mixed-precision load path against the FP64
+    path: notched Q4 32x32 plate, 4 of 8 tension steps, both to ||R_f|| <= 1e-11."""
+    case = W.make_case(3, n=32)
+    case.n_steps = 8
+    out = {}
+    for prec in ("fp64", precision):
+        ctx = G.Context.from_case(case)
+        u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+        iters = 0
+        for n in range(1, 5):
+            u0 = W.uniaxial_predictor(case, u.cpu().numpy(), n)
+            u.copy_(torch.as_tensor(u0, device=ctx.dev))
+            bd, bv = W.uniaxial_bc(case, n)
+            rep = ctx.newton_step(u, phi, kap, bd, bv, prec, reaction_dofs=W.reaction_dofs(case),
+                                  newton_rtol=0.0, newton_atol=1e-11, krylov_rtol=1e-13)
+            iters += rep["newton_iters"]
+        torch.cuda.synchronize()
+        out[prec] = (u.clone(), phi.clone(), rep["reaction"], iters)
+        ctx.close()
+    (u0, p0, r0, i0), (u1, p1, r1, i1) = out["fp64"], out[precision]
+    return dict(displacement=rel_err(u1, u0), phi=rel_err(p1, p0), reaction=abs(r1 - r0) / abs(r0),
+                newton_iters_fp64=i0, newton_iters_mixed=i1,
+                path="notched Q4 32x32, 4 tension steps, ||R_f|| <= 1e-11")
+
+
+def bench_mixed(G, W, torch, ctx, fields, out, ref, steps, warmup, nq):
+    res = {}
+    for prec in ("bf16", "fp16"):
+        try:
+            ms, prof = time_assembly(ctx, fields, out, prec, steps, warmup, torch)
+        except G.GedmgError as e:
+            res[prec] = f"unavailable: {e}"
+            continue
+        R, K, _ = out
+        errs = dict(residual=rel_err(R, ref[0]), tangent=rel_err(K, ref[1]))
+        log(f"{prec}: {ms / steps:.3f} ms/step, residual err {errs['residual']:.2e} "
+            f"tangent err {errs['tangent']:.2e}; converged-displacement check")
+        errs.update(mixed_newton_error(G, W, torch, prec))
+        res[prec] = dict(value=nq / (ms / steps * 1e-3), unit="qp/s", ms_per_step=ms / steps,
+                         jet_ms=per_call(prof, "jets"), element_ms=per_call(prof, "elements"),
+                         error_vs_fp64=errs)
+    return res
+
+
+def bench_adjoint(G, W, torch, checkpoint_every=5):
+    """Load-path adjoint on the 128x128 Q4 workload: targets from the forward
+    run with the seeded perturbed weights, gradient at the seeded weights."""
+    import numpy as np
+
+    case = W.make_case(5)
+    steps = case.n_steps
+    ctx = G.Context.from_case(case)
+    du = np.stack([W.uniaxial_predictor(case, np.zeros_like(case.u), n) for n in range(1, steps + 1)])
+    bcs = [W.uniaxial_bc(case, n) for n in range(1, steps + 1)]
+    rd = W.reaction_dofs(case)
+    ctx.set_params(case.extra["theta_e_star"], case.extra["theta_y_star"])
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    targets = []
+    for n in range(1, steps + 1):
+        u += torch.as_tensor(du[n - 1], device=ctx.dev)
+        targets.append(ctx.newton_step(u, phi, kap, *bcs[n - 1], reaction_dofs=rd)["reaction"])
+    ctx.set_params(case.theta_e, case.theta_y)
+    path = G.LoadPath(case.u, case.phi, case.kappa, bcs, rd, targets, predictor_du=du)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss, ge, gy, rep = ctx.adjoint(path, checkpoint_every=checkpoint_every)
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return dict(workload=case.name, elements=case.mesh.n_elems, steps=steps, checkpoint_every=checkpoint_every,
+                n_params=int(ge.size + gy.size), s_per_step=dt / steps, total_s=dt, loss=loss,
+                forward_s=rep["t_forward_s"], recompute_s=rep["t_recompute_s"], reverse_s=rep["t_reverse_s"],
+                newton_iters=rep["newton_iters_total"], krylov_iters=rep["krylov_iters_total"])
+
+
 def cpu_baseline(case, n_elems):
     """The oracle, as it stands, on the first n_elems elements of the workload."""
     import torch
@@ -81,18 +179,45 @@ def cpu_baseline(case, n_elems):
                        f"({nq} qp) of the 64^3 Hex8 workload, {dt:.1f} s")
 
 
+def jet_traffic(launch_bytes_alg):
+    """HBM bytes per jet launch from the committed rocprofv3 counter summary,
+    if it was taken on the current jet source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
+        with open(JET_SOURCE, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError, IndexError):
+        return None
+    if rec.get("jet_source_sha256") != digest:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def copy_probe(torch, mib=1024, reps=3):
+    """A plain device copy of known size for scaling the HBM byte counters."""
+    a = torch.empty(mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy probe: {reps} copies of {mib} MiB")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-elems", type=int, default=8192)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "bf16", "fp16"])
+    ap.add_argument("--cpu-sample-elems", type=int, default=49152)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded "
-              f"design is described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build measures the "
+              f"single-GPU hot path; the sharded design is described, not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -101,64 +226,62 @@ def main():
     from paper_2604_03411_amd import gedmg as G
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(torch)
     case = W.make_case(4)
     mesh = case.mesh
     nq = mesh.n_elems * mesh.nqp
-    print(f"[bench] {case.name}: {mesh.n_elems} elements, {nq} qp, building context", file=sys.stderr,
-          flush=True)
+    log(f"{case.name}: {mesh.n_elems} elements, {nq} qp, building context")
     ctx = G.Context.from_case(case)
     fields = ctx.fields(case.u, case.phi, case.kappa)
     out = (torch.empty(ctx.ndof, dtype=torch.float64, device="cuda"),
            torch.empty(ctx.nnz, dtype=torch.float64, device="cuda"),
            torch.empty(mesh.n_elems, mesh.nqp, dtype=torch.float64, device="cuda"))
-    print(f"[bench] nnz {ctx.nnz}; timing {args.steps} {args.precision} assemblies", file=sys.stderr,
-          flush=True)
-    ms, prof = time_assembly(ctx, fields, out, args.precision, args.steps, args.warmup, torch)
+    log(f"nnz {ctx.nnz}; timing {args.steps} FP64 assemblies")
+    ms, prof = time_assembly(ctx, fields, out, "fp64", args.steps, args.warmup, torch)
     ms_step = ms / args.steps
     value = nq / (ms_step * 1e-3)
     H, L = case.energy.width, case.energy.n_hidden
-    jet_ms = prof["jets"] / max(prof["calls"], 1)
-    elem_ms = prof["elements"] / max(prof["calls"], 1)
-    fill_ms = prof["fills"] / max(prof["calls"], 1)
-    in_ms = prof["inputs"] / max(prof["calls"], 1)
+    jet_ms, elem_ms = per_call(prof, "jets"), per_call(prof, "elements")
+    fill_ms, in_ms = per_call(prof, "fills"), per_call(prof, "inputs")
     flops = jet_flops_per_qp(H, L) * nq
-    peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_BF16_TFLOPS
     jet_tf = flops / (jet_ms * 1e-3) / 1e12
-    dominant = "energy_jet" if jet_ms >= elem_ms else "element"
-    roofline = dict(bound="mfma", achieved=round(jet_tf, 3), peak=peak, unit="TFLOP/s",
-                    frac=round(jet_tf / peak, 4), traffic=None, kernel=f"jet_{args.precision}_kernel",
-                    flops_per_qp=jet_flops_per_qp(H, L), ms_per_launch=round(jet_ms, 4))
-    print(f"[bench] {ms_step:.3f} ms/step; phases ms: inputs {in_ms:.3f} jets {jet_ms:.3f} "
-          f"elements {elem_ms:.3f} fills {fill_ms:.3f}", file=sys.stderr, flush=True)
+    traffic = jet_traffic(nq * (3 + 10) * 8)
+    roofline = dict(bound="mfma", achieved=round(jet_tf, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                    frac=round(jet_tf / PEAK_FP64_TFLOPS, 4), traffic=traffic, kernel="jet_f64_kernel",
+                    flops_per_qp=jet_flops_per_qp(H, L), qp_per_launch=nq, ms_per_launch=round(jet_ms, 4))
+    log(f"{ms_step:.3f} ms/step; phases ms: inputs {in_ms:.3f} jets {jet_ms:.3f} elements {elem_ms:.3f} "
+        f"fills {fill_ms:.3f}")
 
     extra = {}
-    if args.precision == "fp64":
-        try:
-            ms2, prof2 = time_assembly(ctx, fields, out, "bf16", args.steps, args.warmup, torch)
-            extra["mixed_bf16"] = dict(value=nq / (ms2 / args.steps * 1e-3), ms_per_step=ms2 / args.steps,
-                                       speedup_vs_fp64=ms / ms2,
-                                       jet_ms=prof2["jets"] / max(prof2["calls"], 1),
-                                       element_ms=prof2["elements"] / max(prof2["calls"], 1))
-        except G.GedmgError as e:
-            extra["mixed_bf16"] = f"unavailable: {e}"
+    if not args.no_mixed:
+        ref = (out[0].clone(), out[1].clone())
+        extra["mixed"] = bench_mixed(G, W, torch, ctx, fields, out, ref, args.steps, args.warmup, nq)
+        del ref
+    ctx.close()
+    del out, fields
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        log("load-path adjoint, 128x128 Q4, 20 steps, checkpoint every 5")
+        extra["adjoint"] = bench_adjoint(G, W, torch)
+        log(f"adjoint {extra['adjoint']['s_per_step']:.3f} s/step")
 
     cpu = None
     if not args.no_cpu_baseline:
-        print(f"[bench] timing the oracle on {args.cpu_sample_elems} elements", file=sys.stderr, flush=True)
+        log(f"timing the oracle on {args.cpu_sample_elems} elements")
         cpu = cpu_baseline(case, args.cpu_sample_elems)
 
     line = dict(
         metric="qp residual+tangent evals/sec", value=value, unit="qp/s", n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True,
-        scaling="weak", vs_baseline=None, dtype="f64" if args.precision == "fp64" else args.precision,
-        data="synthetic",
-        config=dict(workload=case.name, elements=mesh.n_elems, qp=nq, dofs=ctx.ndof, nnz=ctx.nnz,
+        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=case.name, elements=mesh.n_elems, qp=nq, dofs=int(mesh.ndof), nnz=int(ctx.nnz),
                     energy_net=f"3-{H}x{L}-1", yield_net=f"1-{case.yield_.width}x{case.yield_.n_hidden}-1",
-                    precision=args.precision),
-        phases_ms=dict(inputs=in_ms, jets=jet_ms, elements=elem_ms, fills=fill_ms, dominant=dominant),
+                    precision="fp64"),
+        phases_ms=dict(inputs=in_ms, jets=jet_ms, elements=elem_ms, fills=fill_ms,
+                       dominant="energy_jet" if jet_ms >= elem_ms else "element"),
         roofline=roofline, cpu_baseline=cpu, **extra)
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":
