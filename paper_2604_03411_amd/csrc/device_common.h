@@ -37,47 +37,175 @@ __device__ __forceinline__ void shape_at(int a, int q, double& N, double dN[DIM]
   }
 }
 
-// softplus(a0 + d) - softplus(a0) and the logistic pair (s, 1 - s) at a0 + d,
-// from a0 and s0 = logistic(a0), sb0 = logistic(-a0).  For increments that
-// keep 1 + y above 1/2 the expm1/log1p form is used (relative precision of
-// small increments, no overflow); larger increments (|d| of order one or more)
-// take the direct difference, which then loses nothing.
-template <typename T>
-__device__ __forceinline__ T softplus_pair(T a, T& s, T& sb) {
-  const T e = exp(-fabs(a));
-  const T inv = T(1) / (T(1) + e);
-  s = (a >= T(0)) ? inv : e * inv;
-  sb = (a >= T(0)) ? e * inv : inv;
-  return fmax(a, T(0)) + log1p(e);
+// ------------------------------------------------------------------ FP64 math
+// Elementary functions for the network activations, written for the argument
+// ranges the kernels use.
+//   exp(t), expm1(t) for t <= 0: Cody-Waite reduction t = n ln2 + r with
+//     |r| <= ln2/2 (ln2 split so that n * kLn2Hi is exact), Taylor series of
+//     expm1(r) through r^13/13! (truncation below 2^-60 relative), scaling by
+//     2^n; expm1 adds 2^n - 1, exact for the n that occur.
+//   log1p(y) for y in (-0.5, 1]: log1p(y) = 2 atanh(s), s = y / (2 + y),
+//     |s| <= 1/3, atanh series in s^2 through s^32 / 33.
+//   reciprocals: hardware estimate refined by two Newton steps.
+// Errors stay within 2 ulp on these ranges; NaN inputs propagate.
+constexpr double kInvLn2 = 1.4426950408889634;
+constexpr double kLn2Hi = 6.93147180369123816490e-01;
+constexpr double kLn2Lo = 1.90821492927058770002e-10;
+
+__device__ __forceinline__ double rcp_d(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return r;
 }
 
-template <typename T>
-__device__ __forceinline__ T delta_softplus(T d, T a0, T s0, T sb0, T& s, T& sb) {
-  const bool neg = d <= T(0);
-  const T e = expm1(neg ? d : -d);
-  const T y = (neg ? s0 : sb0) * e;
-  if (y > T(-0.5)) {
-    const T inv = T(1) / (T(1) + y);
+__device__ __forceinline__ double div_d(double a, double b) {
+  const double r = rcp_d(b);
+  const double q = a * r;
+  return fma(r, fma(-b, q, a), q);
+}
+
+// Reduced argument and expm1 of it; n such that t = n ln2 + r.  Valid for
+// t <= 700 (arguments below -800 are clamped; the results are then 0 / -1).
+__device__ __forceinline__ double expm1_reduced(double t, double& n) {
+  t = (t < -800.0) ? -800.0 : ((t > 700.0) ? 700.0 : t);
+  n = rint(t * kInvLn2);
+  const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, t));
+  constexpr double c13 = 1.0 / 6227020800.0, c12 = 1.0 / 479001600.0, c11 = 1.0 / 39916800.0,
+                   c10 = 1.0 / 3628800.0, c9 = 1.0 / 362880.0, c8 = 1.0 / 40320.0, c7 = 1.0 / 5040.0,
+                   c6 = 1.0 / 720.0, c5 = 1.0 / 120.0, c4 = 1.0 / 24.0, c3 = 1.0 / 6.0, c2 = 0.5;
+  double p = fma(c13, r, c12);
+  p = fma(p, r, c11);
+  p = fma(p, r, c10);
+  p = fma(p, r, c9);
+  p = fma(p, r, c8);
+  p = fma(p, r, c7);
+  p = fma(p, r, c6);
+  p = fma(p, r, c5);
+  p = fma(p, r, c4);
+  p = fma(p, r, c3);
+  p = fma(p, r, c2);
+  return fma(r * r, p, r);
+}
+
+__device__ __forceinline__ double exp_nonpos(double t) {
+  double n;
+  const double q = expm1_reduced(t, n);
+  return ldexp(1.0 + q, (int)n);
+}
+
+__device__ __forceinline__ double expm1_nonpos(double t) {
+  double n;
+  const double q = expm1_reduced(t, n);
+  const int ni = (int)n;
+  return (n == 0.0) ? q : ldexp(q, ni) + (ldexp(1.0, ni) - 1.0);
+}
+
+__device__ __forceinline__ double log1p_small(double y) {
+  const double s = div_d(y, 2.0 + y);
+  const double z = s * s;
+  double p = fma(1.0 / 33.0, z, 1.0 / 31.0);
+  p = fma(p, z, 1.0 / 29.0);
+  p = fma(p, z, 1.0 / 27.0);
+  p = fma(p, z, 1.0 / 25.0);
+  p = fma(p, z, 1.0 / 23.0);
+  p = fma(p, z, 1.0 / 21.0);
+  p = fma(p, z, 1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  const double ts = 2.0 * s;
+  return fma(ts * z, p, ts);
+}
+
+// softplus(a) and the logistic pair (s, 1 - s) at a.
+__device__ __forceinline__ double softplus_pair(double a, double& s, double& sb) {
+  const double e = exp_nonpos(-fabs(a));
+  const double inv = rcp_d(1.0 + e);
+  s = (a >= 0.0) ? inv : e * inv;
+  sb = (a >= 0.0) ? e * inv : inv;
+  return fmax(a, 0.0) + log1p_small(e);
+}
+
+__device__ __forceinline__ float softplus_pair(float a, float& s, float& sb) {
+  const float e = expf(-fabsf(a));
+  const float inv = 1.0f / (1.0f + e);
+  s = (a >= 0.0f) ? inv : e * inv;
+  sb = (a >= 0.0f) ? e * inv : inv;
+  return fmaxf(a, 0.0f) + log1pf(e);
+}
+
+// log(w) for w = 1 + y > 0, given both: y > -1/2 goes through the series in y
+// (relative precision of small y); otherwise w, which is then accurate, is
+// split as m 2^k with m in [3/4, 3/2) and log(w) = k ln2 + log1p(m - 1).
+__device__ __forceinline__ double log1p_pair(double y, double w) {
+  int k;
+  double m = frexp(w, &k);
+  const bool low = m < 0.75;
+  m = low ? 2.0 * m : m;
+  k = low ? k - 1 : k;
+  const bool small = y > -0.5;
+  const double f = small ? y : m - 1.0;
+  const double kk = small ? 0.0 : (double)k;
+  return fma(kk, kLn2Hi, fma(kk, kLn2Lo, log1p_small(f)));
+}
+
+// softplus(a0 + d) - softplus(a0) and the logistic pair (s, 1 - s) at
+// a = a0 + d, from s0 = logistic(a0) and sb0 = logistic(-a0), without branches.
+// For a <= 0 the increment is log(w) with w = sb0 + s0 e^d = 1 + s0 expm1(d);
+// for a > 0, by softplus(a) = a + softplus(-a), it is d + log(w) with
+// w = s0 + sb0 e^-d.  Choosing the form by the sign of a keeps the increment
+// free of cancellation (the logarithm carries the whole increment where the
+// network is in its flat half), w is a sum of non-negative terms, and the
+// logistic pair is (s0 e^d / w, sb0 / w) or (s0 / w, sb0 e^-d / w).
+__device__ __forceinline__ double delta_softplus(double d, double a0, double s0, double sb0, double& s,
+                                                 double& sb) {
+  const bool fa = a0 + d <= 0.0;
+  double n;
+  const double q = expm1_reduced(fa ? d : -d, n);
+  const int ni = (int)n;
+  const double E = ldexp(1.0 + q, ni);
+  const double M = (n == 0.0) ? q : ldexp(q, ni) + (ldexp(1.0, ni) - 1.0);
+  const double p = fa ? s0 : sb0, c = fa ? sb0 : s0;
+  const double w = fma(p, E, c);
+  const double inv = rcp_d(w);
+  const double sp = p * E * inv, sc = c * inv;
+  s = fa ? sp : sc;
+  sb = fa ? sc : sp;
+  return (fa ? 0.0 : d) + log1p_pair(p * M, w);
+}
+
+__device__ __forceinline__ float delta_softplus(float d, float a0, float s0, float sb0, float& s, float& sb) {
+  const bool neg = d <= 0.0f;
+  const float e = expm1f(neg ? d : -d);
+  const float y = (neg ? s0 : sb0) * e;
+  if (y > -0.5f) {
+    const float inv = 1.0f / (1.0f + y);
     if (neg) {
-      s = s0 * (T(1) + e) * inv;
+      s = s0 * (1.0f + e) * inv;
       sb = sb0 * inv;
-      return log1p(y);
+      return log1pf(y);
     }
     s = s0 * inv;
-    sb = sb0 * (T(1) + e) * inv;
-    return d + log1p(y);
+    sb = sb0 * (1.0f + e) * inv;
+    return d + log1pf(y);
   }
-  T s_ref, sb_ref;
-  const T za = softplus_pair<T>(a0 + d, s, sb);
-  return za - softplus_pair<T>(a0, s_ref, sb_ref);
+  float s_ref, sb_ref;
+  const float za = softplus_pair(a0 + d, s, sb);
+  return za - softplus_pair(a0, s_ref, sb_ref);
 }
 
 // Plain softplus and logistic (yield network, evaluated directly).
 __device__ __forceinline__ double softplus_d(double a, double& s) {
-  const double e = exp(-fabs(a));
-  const double inv = 1.0 / (1.0 + e);
+  const double e = exp_nonpos(-fabs(a));
+  const double inv = rcp_d(1.0 + e);
   s = (a >= 0.0) ? inv : e * inv;
-  return fmax(a, 0.0) + log1p(e);
+  return fmax(a, 0.0) + log1p_small(e);
 }
 
 // Make LDS writes of this wavefront visible to its own later reads, and keep

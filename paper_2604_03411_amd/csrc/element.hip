@@ -317,8 +317,10 @@ __device__ __forceinline__ void d_row(const Qp& __restrict__ s, const Material& 
 }
 
 // ------------------------------------------------------------------ element kernel
+typedef double d2_t __attribute__((ext_vector_type(2)));
+
 template <int DIM, int YH>
-struct ElemLds {
+struct alignas(16) ElemLds {
   using T = Tr<DIM>;
   double G[8][T::NEN][3];  // grad N per qp
   double N[8][T::NEN];
@@ -508,7 +510,7 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   double kap = kn, dNy = 0.0;
   bool yielded = false;
   {
-    const double f0 = exp(-M.eta * fmax(kn - M.kd, 0.0));
+    const double f0 = exp_nonpos(-M.eta * fmax(kn - M.kd, 0.0));
     const double q0 = psi_e + gb * (phi - kn) / (M.eta * f0);
     double d0;
     const double h0 = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, q0, sc, d0) - kn;
@@ -544,7 +546,7 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
         // Newton correction from the current iterate; the convergence test comes
         // before the bracket safeguard so that a root reached on the bracket's
         // end is accepted rather than bisected away from.
-        const double fk = exp(-M.eta * fmax(k - M.kd, 0.0));
+        const double fk = exp_nonpos(-M.eta * fmax(k - M.kd, 0.0));
         const double dq = gb / (M.eta * fk) * (-1.0 + ((k > M.kd) ? M.eta * (phi - k) : 0.0));
         const double dk = -h / (dNy * dq - 1.0);
         const double tol = 1e-15 * fmax(1.0, fabs(k));
@@ -562,7 +564,7 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
           step1 = fabs(dk);
         }
         k = kn1;
-        const double fk1 = exp(-M.eta * fmax(k - M.kd, 0.0));
+        const double fk1 = exp_nonpos(-M.eta * fmax(k - M.kd, 0.0));
         const double qk = psi_e + gb * (phi - k) / (M.eta * fk1);
         h = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, qk, sc, dNy) - k;
         if (h > 0.0) lo = k; else hi = k;
@@ -572,7 +574,7 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
       kap = k;
     }
   }
-  const double fkap = exp(-M.eta * fmax(kap - M.kd, 0.0));
+  const double fkap = exp_nonpos(-M.eta * fmax(kap - M.kd, 0.0));
   const double fpkap = (kap > M.kd) ? -M.eta * fkap : 0.0;
   double rhoF = 0.0, kphi = 0.0;
   if (yielded) {
@@ -655,13 +657,12 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     const int col = li % T::NDOFE;
     const int rb = (li / T::NDOFE) * RPL;
     const bool own = (DIM == 3 ? true : li < 2 * T::NDOFE) && (slot_base + eslot < a.e_end);
-    if (!own) return;
     const int bnode = col / T::ND, kc = col % T::ND;
     double Kacc[RPL];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) Kacc[t] = 0.0;
 #pragma unroll 1
-    for (int qq = 0; qq < T::NQP; ++qq) {
+    for (int qq = 0; qq < (own ? T::NQP : 0); ++qq) {
       const int gq = eslot * 4 + qq;
       // B[:, col] nonzeros -> T = D B[:, col]
       double Tz[T::NZ];
@@ -699,15 +700,55 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
         Kacc[t] += jw * v;
       }
     }
-    const int ae = a.perm[slot_base + eslot];
-    const int32_t* blk = a.blk + (long)ae * T::NEN * T::NEN;
+    // Stage K_e in LDS (the D buffer is free now), then write it one CSR
+    // block row segment (the ND columns of one element node) per lane: wide,
+    // mostly contiguous accesses.  The first colour that touches a block
+    // stores it, later colours read-modify-write it, so K needs no clearing.
+    double* Ke = &S.D[0][0][0] + eslot * T::NDOFE * T::NDOFE;
+    wave_lds_sync();
+    if (own) {
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int r = rb + t;
+      for (int t = 0; t < RPL; ++t) Ke[(rb + t) * T::NDOFE + col] = Kacc[t];
+    }
+  }
+  wave_lds_sync();
+  {
+    constexpr int NSEG = T::EPW * T::NDOFE * T::NEN;  // segments per wavefront
+#pragma unroll 1
+    for (int sg = lane; sg < NSEG; sg += 64) {
+      const int es = sg / (T::NDOFE * T::NEN);
+      const int rem = sg - es * (T::NDOFE * T::NEN);
+      const int r = rem / T::NEN, bnode = rem % T::NEN;
+      if (slot_base + es >= a.e_end) continue;
+      const int ae = a.perm[slot_base + es];
       const int an = r / T::ND, cr = r % T::ND;
       const int nodea = a.conn[(long)ae * T::NEN + an];
-      const long off = (long)blk[an * T::NEN + bnode] + (long)cr * a.rowstride[nodea] + kc;
-      a.K[off] += Kacc[t];
+      const long off = (long)a.blk[((long)ae * T::NEN + an) * T::NEN + bnode] + (long)cr * a.rowstride[nodea];
+      const double* src = &S.D[0][0][0] + es * T::NDOFE * T::NDOFE + r * T::NDOFE + bnode * T::ND;
+      const bool first = (a.first[ae] >> (an * T::NEN + bnode)) & 1ull;
+      if constexpr (T::ND == 4) {
+        // 32-byte aligned segment (block rows start at multiples of 4 entries;
+        // the caller's K is 16-byte aligned)
+        const d2_t* s2 = reinterpret_cast<const d2_t*>(src);
+        d2_t* k2 = reinterpret_cast<d2_t*>(a.K + off);
+        d2_t v0 = s2[0], v1 = s2[1];
+        if (!first) {
+          v0 += k2[0];
+          v1 += k2[1];
+        }
+        k2[0] = v0;
+        k2[1] = v1;
+      } else {
+        double v[T::ND];
+#pragma unroll
+        for (int k = 0; k < T::ND; ++k) v[k] = src[k];
+        if (!first) {
+#pragma unroll
+          for (int k = 0; k < T::ND; ++k) v[k] += a.K[off + k];
+        }
+#pragma unroll
+        for (int k = 0; k < T::ND; ++k) a.K[off + k] = v[k];
+      }
     }
   }
 }

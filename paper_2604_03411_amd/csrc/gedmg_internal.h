@@ -91,6 +91,7 @@ struct ElemArgs {
   const int32_t* perm;       // elements sorted by colour
   const int32_t* blk;        // [n_elems][nen][nen] CSR offset of block (a,b) row 0
   const int32_t* rowstride;  // [n_nodes] CSR row length of the node's rows
+  const uint64_t* first;     // [n_elems] bit a*nen+b: this element is the first (lowest colour) to write block (a,b)
   const double* u;
   const double* phi;
   const double* kappa_n;
@@ -146,6 +147,7 @@ struct gedmg_ctx {
   int32_t* dperm = nullptr;
   int32_t* dblk = nullptr;
   int32_t* drowstride = nullptr;
+  uint64_t* dfirst = nullptr;          // first-writer bits per element (see ElemArgs)
   int32_t* drowptr = nullptr;
   int32_t* dcol = nullptr;
   double* denet = nullptr;             // packed energy network

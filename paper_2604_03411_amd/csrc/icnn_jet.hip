@@ -68,7 +68,7 @@ __global__ __launch_bounds__(WAVES * 64) void jet_f64_kernel(JetArgs a) {
     const double x[3] = {xs[j * 3], xs[j * 3 + 1], xs[j * 3 + 2]};
 
     double sS[L][4], sB[L][4];   // logistic pair at a_k, rows r of this lane
-    double Jt[L][4][3];          // da_k/dx
+    double Jt[L][4][3];          // da_k/dx for k >= 1 (layer 0: the rows of W0)
     double dz[4], zt[4][3];
 
     // layer 1: a_1 = W0 x + b0 (vector ALU)
@@ -77,11 +77,11 @@ __global__ __launch_bounds__(WAVES * 64) void jet_f64_kernel(JetArgs a) {
       const int n = nt * 16 + lg + 4 * r;
       const double w0 = net[lay.W0 + n * 3], w1 = net[lay.W0 + n * 3 + 1], w2 = net[lay.W0 + n * 3 + 2];
       const double da = w0 * x[0] + w1 * x[1] + w2 * x[2];
-      dz[r] = delta_softplus<double>(da, net[lay.a0 + n], net[lay.s0 + n], net[lay.sb0 + n],
+      dz[r] = delta_softplus(da, net[lay.a0 + n], net[lay.s0 + n], net[lay.sb0 + n],
                                      sS[0][r], sB[0][r]);
-      Jt[0][r][0] = w0; Jt[0][r][1] = w1; Jt[0][r][2] = w2;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) zt[r][i] = sS[0][r] * Jt[0][r][i];
+      zt[r][0] = sS[0][r] * w0;
+      zt[r][1] = sS[0][r] * w1;
+      zt[r][2] = sS[0][r] * w2;
     }
 
 #pragma unroll
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(WAVES * 64) void jet_f64_kernel(JetArgs a) {
         const double da = acc[0][r] + wx[0] * x[0] + wx[1] * x[1] + wx[2] * x[2];
 #pragma unroll
         for (int i = 0; i < 3; ++i) Jt[k][r][i] = acc[1 + i][r] + wx[i];
-        dz[r] = delta_softplus<double>(da, net[lay.a0 + k * H + n], net[lay.s0 + k * H + n],
+        dz[r] = delta_softplus(da, net[lay.a0 + k * H + n], net[lay.s0 + k * H + n],
                                        net[lay.sb0 + k * H + n],
                                        sS[k][r], sB[k][r]);
 #pragma unroll
@@ -145,7 +145,17 @@ __global__ __launch_bounds__(WAVES * 64) void jet_f64_kernel(JetArgs a) {
         for (int r = 0; r < 4; ++r) {
           abar[r] = zbar[r] * sS[k][r];
           const double c2 = abar[r] * sB[k][r];
-          const double* Jr = Jt[k][r];
+          double Jr[3];
+          if (k == 0) {
+            const int n = nt * 16 + lg + 4 * r;
+            Jr[0] = net[lay.W0 + n * 3];
+            Jr[1] = net[lay.W0 + n * 3 + 1];
+            Jr[2] = net[lay.W0 + n * 3 + 2];
+          } else {
+            Jr[0] = Jt[k][r][0];
+            Jr[1] = Jt[k][r][1];
+            Jr[2] = Jt[k][r][2];
+          }
           part[4] += c2 * Jr[0] * Jr[0];
           part[5] += c2 * Jr[1] * Jr[1];
           part[6] += c2 * Jr[2] * Jr[2];

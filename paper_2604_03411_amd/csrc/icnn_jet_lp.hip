@@ -113,7 +113,7 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
       const float w0 = (float)net[lay.W0 + n * 3], w1 = (float)net[lay.W0 + n * 3 + 1],
                   w2 = (float)net[lay.W0 + n * 3 + 2];
       const float da = w0 * x[0] + w1 * x[1] + w2 * x[2];
-      dz[r] = delta_softplus<float>(da, (float)net[lay.a0 + n], (float)net[lay.s0 + n],
+      dz[r] = delta_softplus(da, (float)net[lay.a0 + n], (float)net[lay.s0 + n],
                                     (float)net[lay.sb0 + n], sS[0][r], sB[0][r]);
       Jt[0][r][0] = w0; Jt[0][r][1] = w1; Jt[0][r][2] = w2;
 #pragma unroll
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
         Jt[k][r][0] = acc[1][r] + wx0;
         Jt[k][r][1] = acc[2][r] + wx1;
         Jt[k][r][2] = acc[3][r] + wx2;
-        dz[r] = delta_softplus<float>(da, (float)net[lay.a0 + k * H + n], (float)net[lay.s0 + k * H + n],
+        dz[r] = delta_softplus(da, (float)net[lay.a0 + k * H + n], (float)net[lay.s0 + k * H + n],
                                       (float)net[lay.sb0 + k * H + n], sS[k][r], sB[k][r]);
 #pragma unroll
         for (int i = 0; i < 3; ++i) zt[r][i] = sS[k][r] * Jt[k][r][i];

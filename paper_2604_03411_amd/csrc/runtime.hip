@@ -149,7 +149,7 @@ int upload_params(gedmg_ctx* c, const double* te, const double* ty) {
 }
 
 void free_all(gedmg_ctx* c) {
-  void* ptrs[] = {c->dX, c->dconn, c->dperm, c->dblk, c->drowstride, c->drowptr, c->dcol,
+  void* ptrs[] = {c->dX, c->dconn, c->dperm, c->dblk, c->drowstride, c->dfirst, c->drowptr, c->dcol,
                   c->denet, c->dynet, c->dw_bf16, c->dw_f16, c->dx, c->djet, c->dstatus};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -265,6 +265,20 @@ int gedmg_create(gedmg_ctx** out, const gedmg_mesh* mesh, const gedmg_material* 
     ncol = std::max(ncol, k + 1);
     for (int a = 0; a < nen; ++a) used[conn[(long)e * nen + a]] |= 1ull << k;
   }
+  // first writer of every node-pair block: the element of lowest colour that
+  // contains both nodes (one element per colour at most, colours run in order)
+  std::vector<uint64_t> first((size_t)ne, 0);
+  {
+    std::vector<int> mincol((size_t)(nnz / nd), 1 << 30);
+    for (int e = 0; e < ne; ++e)
+      for (int ab = 0; ab < nen * nen; ++ab) {
+        const size_t b = (size_t)blk[(size_t)e * nen * nen + ab] / nd;
+        mincol[b] = std::min(mincol[b], color[e]);
+      }
+    for (int e = 0; e < ne; ++e)
+      for (int ab = 0; ab < nen * nen; ++ab)
+        if (mincol[(size_t)blk[(size_t)e * nen * nen + ab] / nd] == color[e]) first[e] |= 1ull << ab;
+  }
   std::vector<int32_t> perm(ne);
   c->color_begin.assign(ncol + 1, 0);
   for (int e = 0; e < ne; ++e) c->color_begin[color[e] + 1]++;
@@ -278,7 +292,8 @@ int gedmg_create(gedmg_ctx** out, const gedmg_mesh* mesh, const gedmg_material* 
   const int64_t nq = (int64_t)ne * c->nqp;
   if ((rc = dalloc(c, &c->dX, (size_t)c->dim * nn)) || (rc = dalloc(c, &c->dconn, (size_t)ne * nen)) ||
       (rc = dalloc(c, &c->dperm, ne)) || (rc = dalloc(c, &c->dblk, blk.size())) ||
-      (rc = dalloc(c, &c->drowstride, nn)) || (rc = dalloc(c, &c->drowptr, rowptr.size())) ||
+      (rc = dalloc(c, &c->drowstride, nn)) || (rc = dalloc(c, &c->dfirst, (size_t)ne)) ||
+      (rc = dalloc(c, &c->drowptr, rowptr.size())) ||
       (rc = dalloc(c, &c->dcol, nnz)) || (rc = dalloc(c, &c->dx, (size_t)nq * 3)) ||
       (rc = dalloc(c, &c->djet, (size_t)nq * 10)) || (rc = dalloc(c, &c->dstatus, 4)))
     return fail(rc);
@@ -287,6 +302,7 @@ int gedmg_create(gedmg_ctx** out, const gedmg_mesh* mesh, const gedmg_material* 
   GEDMG_HIP(c, hipMemcpy(c->dperm, perm.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemcpy(c->dblk, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemcpy(c->drowstride, rowstride.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice));
+  GEDMG_HIP(c, hipMemcpy(c->dfirst, first.data(), sizeof(uint64_t) * ne, hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemcpy(c->drowptr, rowptr.data(), sizeof(int32_t) * rowptr.size(), hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemcpy(c->dcol, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemset(c->dstatus, 0, 4 * sizeof(int)));
@@ -337,6 +353,10 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
     c->err = "unknown precision";
     return GEDMG_E_ARG;
   }
+  if (reinterpret_cast<uintptr_t>(K_vals) % 16 != 0) {
+    c->err = "K_vals must be 16-byte aligned";
+    return GEDMG_E_ARG;
+  }
   hipEvent_t ev[5] = {};
   if (c->prof) {
     for (int i = 0; i < 5; ++i) {
@@ -347,7 +367,6 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
     GEDMG_HIP(c, hipEventRecord(ev[0], c->stream));
   }
   GEDMG_HIP(c, hipMemsetAsync(R, 0, sizeof(double) * c->ndof, c->stream));
-  if (K_vals) GEDMG_HIP(c, hipMemsetAsync(K_vals, 0, sizeof(double) * c->nnz, c->stream));
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[1], c->stream));
   KinArgs ka{c->dX, c->dconn, u, c->n_nodes, c->n_elems, c->dx, c->dstatus};
   GEDMG_HIP(c, launch_qp_inputs(c->dim, ka, c->stream));
@@ -358,6 +377,7 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[3], c->stream));
   ElemArgs ea{};
   ea.X = c->dX; ea.conn = c->dconn; ea.perm = c->dperm; ea.blk = c->dblk; ea.rowstride = c->drowstride;
+  ea.first = c->dfirst;
   ea.u = u; ea.phi = phi; ea.kappa_n = kappa_n; ea.jet = c->djet; ea.ynet = c->dynet;
   ea.R = R; ea.K = K_vals; ea.kappa_out = kappa_trial; ea.status = c->dstatus;
   ea.n_nodes = c->n_nodes; ea.n_elems = c->n_elems;
