@@ -71,6 +71,9 @@ struct JetArgs {
   double* jet;           // [nq][10]: N(x)-N(0), dN/dx (3), d2N/dx2 (xx,yy,zz,xy,xz,yz)
   const double* net;     // packed effective network (double)
   const uint16_t* w16;   // [L-1][H][H+8] low-precision copies of Wz (bf16 or fp16 bits)
+  const double* wop;     // [L-1][2][H/16][H/4][64] FP64 hidden weights in matrix-core operand
+                         // order: [..][0] forward W[16t + l%16][4s + l/16], [..][1] backward
+                         // W[4s + l/16][16t + l%16] (lane l of output tile t, step s)
   int nq;
   int L;
   int with_hessian;
@@ -154,6 +157,7 @@ struct gedmg_ctx {
   double* dynet = nullptr;             // packed yield network
   uint16_t* dw_bf16 = nullptr;         // low-precision hidden weights
   uint16_t* dw_f16 = nullptr;
+  double* dwop = nullptr;              // FP64 hidden weights in operand order (JetArgs::wop)
   double* dx = nullptr;                // [nq][3]
   double* djet = nullptr;              // [nq][10]
   int* dstatus = nullptr;

@@ -2,9 +2,11 @@
 // N(x) - N(0), grad_x N and the Hessian d2N/dx2 of the input-convex network
 // (Sec. 4.2.1; the hidden->hidden products are the dense part of the path).
 //
-// Per block: tiles of 16 neurons x 16 quadrature points; wave w owns neuron
-// tile (w % NT) of qp tile (w / NT) in every layer, so per-layer quantities
-// (logistic pairs and input Jacobians) stay in that wave's registers.  The
+// Per block: one tile of 16 quadrature points; wave w owns neuron tile w in
+// every layer, so per-layer quantities (logistic pairs and input Jacobians)
+// stay in that wave's registers.  Blocks are small (H/16 waves), so several
+// run on a compute unit and one block's matrix products overlap another's
+// vector work.  The
 // FP64 16x16x4 product returns row (l / 16 + 4 r) of column (l % 16) in
 // accumulator r of lane l, so lane l owns neurons nt*16 + l/16 + 4 r.
 //   forward : 4 columns per qp -- the activation increment dz = z(x) - z(0)
@@ -12,7 +14,8 @@
 //   backward: 1 column -- zbar_k = dN/dz_k;
 //   Hessian : sum_k J_k^T diag(zbar_k s''(a_k)) J_k, J_k = da_k/dx
 // (5 matrix columns per layer instead of the 10 of a forward second-order
-// jet).  Hidden weights are staged once per persistent block in LDS.
+// jet).  Hidden weights are read as matrix-core operands straight from a
+// lane-ordered copy (one coalesced, cache-resident load per step).
 //
 // Activations are carried as increments over the reference state x = 0, so
 // N(x) - N(0) keeps relative precision (delta_softplus, reference constants
@@ -24,40 +27,33 @@ namespace gedmg {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-template <int H, int L, int WAVES>
+template <int H, int L>
 struct JetCfg {
-  static constexpr int NT = H / 16;
-  static constexpr int NQT = WAVES / NT;
-  static constexpr int QB = 16 * NQT;      // quadrature points per batch
-  static constexpr int HP = H + 1;         // padded LDS row (doubles)
-  static constexpr int W_DBL = (L - 1) * H * HP;
-  static constexpr int Z_DBL = 4 * H * QB;
+  static constexpr int NT = H / 16;        // neuron tiles = waves per block
+  static constexpr int WAVES = NT;
+  static constexpr int QB = 16;            // quadrature points per batch
+  static constexpr int QP = QB + 2;        // padded activation row (doubles)
+  static constexpr int Z_DBL = 4 * H * QP;
   static constexpr int X_DBL = QB * 3;
-  static constexpr int LDS_BYTES = 8 * (W_DBL + Z_DBL + X_DBL);
-  static_assert(WAVES % NT == 0, "waves must cover the neuron tiles");
+  static constexpr int LDS_BYTES = 8 * (Z_DBL + X_DBL);
   static_assert(NT * QB * 10 <= Z_DBL, "reduction buffer aliases the activation buffer");
 };
 
-template <int H, int L, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void jet_f64_kernel(JetArgs a) {
-  using C = JetCfg<H, L, WAVES>;
-  constexpr int NT = C::NT, QB = C::QB, HP = C::HP;
+template <int H, int L>
+__global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
+  using C = JetCfg<H, L>;
+  constexpr int NT = C::NT, QB = C::QB, QP = C::QP, NS = H / 4;
   extern __shared__ double lds[];
-  double* Wl = lds;
-  double* Zs = Wl + C::W_DBL;
+  double* Zs = lds;
   double* xs = Zs + C::Z_DBL;
   double* red = Zs;  // reused after the backward pass
   const NetLayout lay = make_layout_hd(3, H, L, 3);
   const double* __restrict__ net = a.net;
-  for (int k = 1; k < L; ++k)
-    for (int idx = threadIdx.x; idx < H * H; idx += blockDim.x)
-      Wl[(k - 1) * H * HP + (idx / H) * HP + (idx % H)] = net[lay.Wz[k] + idx];
-  __syncthreads();
-
+  const double* __restrict__ wop = a.wop;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nt = wave % NT, qt = wave / NT;
+  const int nt = wave;
   const int li = lane & 15, lg = lane >> 4;
-  const int j = qt * 16 + li;  // qp column in the batch
+  const int j = li;  // qp column in the batch
   const int nbatch = (a.nq + QB - 1) / QB;
 
   for (int batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
@@ -89,22 +85,22 @@ __global__ __launch_bounds__(WAVES * 64) void jet_f64_kernel(JetArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int n = nt * 16 + lg + 4 * r;
-        Zs[n * QB + j] = dz[r];
+        Zs[n * QP + j] = dz[r];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) Zs[(1 + i) * H * QB + n * QB + j] = zt[r][i];
+        for (int i = 0; i < 3; ++i) Zs[(1 + i) * H * QP + n * QP + j] = zt[r][i];
       }
       __syncthreads();
       d4_t acc[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[c] = d4_t{0.0, 0.0, 0.0, 0.0};
-      const double* Wk = Wl + (k - 1) * H * HP + (nt * 16 + li) * HP + lg;
-#pragma unroll 4
-      for (int s = 0; s < H / 4; ++s) {
-        const double av = Wk[4 * s];
-        const int zb = (4 * s + lg) * QB + qt * 16 + li;
+      const double* Wk = wop + ((size_t)((k - 1) * 2) * NT + nt) * NS * 64 + lane;
+#pragma unroll 8
+      for (int s = 0; s < NS; ++s) {
+        const double av = Wk[s * 64];
+        const int zb = (4 * s + lg) * QP + li;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Zs[c * H * QB + zb], acc[c], 0, 0, 0);
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Zs[c * H * QP + zb], acc[c], 0, 0, 0);
       }
       __syncthreads();
 #pragma unroll
@@ -165,15 +161,13 @@ __global__ __launch_bounds__(WAVES * 64) void jet_f64_kernel(JetArgs a) {
         }
         if (k > 0) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) Zs[(nt * 16 + lg + 4 * r) * QB + j] = abar[r];
+          for (int r = 0; r < 4; ++r) Zs[(nt * 16 + lg + 4 * r) * QP + j] = abar[r];
           __syncthreads();
           d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
-          const double* Wt = Wl + (k - 1) * H * HP + lg * HP + nt * 16 + li;
-#pragma unroll 4
-          for (int s = 0; s < H / 4; ++s)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wt[4 * s * HP],
-                                                        Zs[(4 * s + lg) * QB + qt * 16 + li], acc, 0,
-                                                        0, 0);
+          const double* Wt = wop + ((size_t)((k - 1) * 2 + 1) * NT + nt) * NS * 64 + lane;
+#pragma unroll 8
+          for (int s = 0; s < NS; ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wt[s * 64], Zs[(4 * s + lg) * QP + li], acc, 0, 0, 0);
           __syncthreads();
 #pragma unroll
           for (int r = 0; r < 4; ++r) zbar[r] = acc[r];
@@ -206,33 +200,33 @@ __global__ __launch_bounds__(WAVES * 64) void jet_f64_kernel(JetArgs a) {
   }
 }
 
-template <int H, int L, int WAVES>
+template <int H, int L>
 static hipError_t launch_f64(const JetArgs& a, hipStream_t s, int num_cu) {
-  using C = JetCfg<H, L, WAVES>;
+  using C = JetCfg<H, L>;
   const int nbatch = (a.nq + C::QB - 1) / C::QB;
-  int per_cu = (160 * 1024) / C::LDS_BYTES;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jet_f64_kernel<H, L>, C::WAVES * 64,
+                                                              C::LDS_BYTES);
+  if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   int grid = num_cu * per_cu;
   if (grid > nbatch) grid = nbatch;
   if (grid <= 0) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute((const void*)jet_f64_kernel<H, L, WAVES>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((jet_f64_kernel<H, L, WAVES>), dim3(grid), dim3(WAVES * 64), C::LDS_BYTES, s, a);
+  hipLaunchKernelGGL((jet_f64_kernel<H, L>), dim3(grid), dim3(C::WAVES * 64), C::LDS_BYTES, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_energy_jet_f64(int H, const JetArgs& a, hipStream_t s, int num_cu) {
   switch (H * 10 + a.L) {
-    case 161: return launch_f64<16, 1, 4>(a, s, num_cu);
-    case 162: return launch_f64<16, 2, 4>(a, s, num_cu);
-    case 163: return launch_f64<16, 3, 4>(a, s, num_cu);
-    case 321: return launch_f64<32, 1, 4>(a, s, num_cu);
-    case 322: return launch_f64<32, 2, 4>(a, s, num_cu);
-    case 323: return launch_f64<32, 3, 4>(a, s, num_cu);
-    case 641: return launch_f64<64, 1, 8>(a, s, num_cu);
-    case 642: return launch_f64<64, 2, 8>(a, s, num_cu);
-    case 643: return launch_f64<64, 3, 8>(a, s, num_cu);
+    case 161: return launch_f64<16, 1>(a, s, num_cu);
+    case 162: return launch_f64<16, 2>(a, s, num_cu);
+    case 163: return launch_f64<16, 3>(a, s, num_cu);
+    case 321: return launch_f64<32, 1>(a, s, num_cu);
+    case 322: return launch_f64<32, 2>(a, s, num_cu);
+    case 323: return launch_f64<32, 3>(a, s, num_cu);
+    case 641: return launch_f64<64, 1>(a, s, num_cu);
+    case 642: return launch_f64<64, 2>(a, s, num_cu);
+    case 643: return launch_f64<64, 3>(a, s, num_cu);
     default: return hipErrorInvalidValue;
   }
 }

@@ -136,6 +136,18 @@ int upload_params(gedmg_ctx* c, const double* te, const double* ty) {
         }
     GEDMG_HIP(c, hipMemcpyAsync(c->dw_bf16, wb.data(), wb.size() * 2, hipMemcpyHostToDevice, c->stream));
     GEDMG_HIP(c, hipMemcpyAsync(c->dw_f16, wf.data(), wf.size() * 2, hipMemcpyHostToDevice, c->stream));
+    // FP64 operands, lane-ordered so each matrix-core step is one coalesced load
+    std::vector<double> wo((size_t)std::max(L - 1, 1) * 2 * H * H, 0.0);
+    for (int k = 1; k < L; ++k)
+      for (int t = 0; t < H / 16; ++t)
+        for (int st = 0; st < H / 4; ++st)
+          for (int l = 0; l < 64; ++l) {
+            const size_t base = ((((size_t)(k - 1) * 2) * (H / 16) + t) * (H / 4) + st) * 64 + l;
+            const size_t tstride = (size_t)(H / 16) * (H / 4) * 64;
+            wo[base] = p[c->elay.Wz[k] + (16 * t + l % 16) * H + 4 * st + l / 16];
+            wo[base + tstride] = p[c->elay.Wz[k] + (4 * st + l / 16) * H + 16 * t + l % 16];
+          }
+    GEDMG_HIP(c, hipMemcpyAsync(c->dwop, wo.data(), wo.size() * 8, hipMemcpyHostToDevice, c->stream));
     GEDMG_HIP(c, hipStreamSynchronize(c->stream));
   }
   if (ty) {
@@ -150,7 +162,7 @@ int upload_params(gedmg_ctx* c, const double* te, const double* ty) {
 
 void free_all(gedmg_ctx* c) {
   void* ptrs[] = {c->dX, c->dconn, c->dperm, c->dblk, c->drowstride, c->dfirst, c->drowptr, c->dcol,
-                  c->denet, c->dynet, c->dw_bf16, c->dw_f16, c->dx, c->djet, c->dstatus};
+                  c->denet, c->dynet, c->dw_bf16, c->dw_f16, c->dwop, c->dx, c->djet, c->dstatus};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -314,7 +326,8 @@ int gedmg_create(gedmg_ctx** out, const gedmg_mesh* mesh, const gedmg_material* 
   c->yraw.assign(c->ylay.n_raw, 0.0);
   const size_t wlp = (size_t)std::max(c->elay.L - 1, 1) * c->elay.H * (c->elay.H + 8);
   if ((rc = dalloc(c, &c->denet, c->elay.total)) || (rc = dalloc(c, &c->dynet, c->ylay.total)) ||
-      (rc = dalloc(c, &c->dw_bf16, wlp)) || (rc = dalloc(c, &c->dw_f16, wlp)))
+      (rc = dalloc(c, &c->dw_bf16, wlp)) || (rc = dalloc(c, &c->dw_f16, wlp)) ||
+      (rc = dalloc(c, &c->dwop, (size_t)std::max(c->elay.L - 1, 1) * 2 * c->elay.H * c->elay.H)))
     return fail(rc);
   if ((rc = upload_params(c, energy->theta, yield->theta))) return fail(rc);
   *out = c;
@@ -371,7 +384,7 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
   KinArgs ka{c->dX, c->dconn, u, c->n_nodes, c->n_elems, c->dx, c->dstatus};
   GEDMG_HIP(c, launch_qp_inputs(c->dim, ka, c->stream));
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[2], c->stream));
-  JetArgs ja{c->dx, c->djet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16,
+  JetArgs ja{c->dx, c->djet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16, c->dwop,
              (int)((int64_t)c->n_elems * c->nqp), c->elay.L, K_vals ? 1 : 0};
   GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[3], c->stream));
@@ -430,7 +443,8 @@ int gedmg_energy_jet(gedmg_ctx* c, const double* x, int64_t n, int precision, do
     c->err = "unknown precision";
     return GEDMG_E_ARG;
   }
-  JetArgs ja{x, jet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16, (int)n, c->elay.L, 1};
+  JetArgs ja{x, jet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16, c->dwop, (int)n,
+             c->elay.L, 1};
   GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
   return GEDMG_OK;
 }
