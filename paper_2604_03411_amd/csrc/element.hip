@@ -649,14 +649,105 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   }
   if (!TANGENT) return;
 
-  // ---------------- element tangent: lane owns one column and a block of rows
-  {
-    constexpr int RPL = (DIM == 3) ? 16 : 6;   // rows per lane
-    const int eslot = (DIM == 3) ? 0 : (lane >> 5);
-    const int li = (DIM == 3) ? lane : (lane & 31);
+  // ---------------- element tangent and its CSR scatter
+  if constexpr (DIM == 3) {
+    // Hex8.  Lane (h, col): column col = (bnode, kc) of K_e and the rows
+    // (an, 2h), (an, 2h + 1) of every element node an.  Per qp the half h
+    // needs T = Jw D B[:, col] only at the z its rows touch: h = 0 (rows of
+    // u1, u2) the z of F rows 1 and 2 (0..5), h = 1 (rows of u3 and phi)
+    // z = 6..12; slot 3 of half 0 is a zero so both halves run one formula:
+    //   K[(an, 2h)]     += G_an . T[0..2]
+    //   K[(an, 2h + 1)] += N_an T[3] + G_an . T[4..6]
+    const int h = lane >> 5, col = lane & 31;
+    const int bnode = col >> 2, kc = col & 3;
+    const int ae = a.perm[slot_base];
+    // the segments this lane writes afterwards: issue their old values now,
+    // so the loads complete while the tangent is integrated
+    constexpr int SPL = T::NDOFE * T::NEN / 64;  // segments per lane
+    long soff[SPL];
+    bool sfirst[SPL];
+    d2_t old0[SPL], old1[SPL];
+#pragma unroll
+    for (int t = 0; t < SPL; ++t) {
+      const int sg = lane + 64 * t;
+      const int r = sg / T::NEN, bn = sg % T::NEN;
+      const int an = r / T::ND, cr = r % T::ND;
+      const int nodea = a.conn[(long)ae * T::NEN + an];
+      soff[t] = (long)a.blk[((long)ae * T::NEN + an) * T::NEN + bn] + (long)cr * a.rowstride[nodea];
+      sfirst[t] = (a.first[ae] >> (an * T::NEN + bn)) & 1ull;
+      old0[t] = d2_t{0.0, 0.0};
+      old1[t] = d2_t{0.0, 0.0};
+      if (!sfirst[t]) {
+        const d2_t* k2 = reinterpret_cast<const d2_t*>(a.K + soff[t]);
+        old0[t] = k2[0];
+        old1[t] = k2[1];
+      }
+    }
+    // column operand: D offsets and weights of B[:, col]
+    int o[4];
+    if (kc < 3) {
+      o[0] = 3 * kc; o[1] = 3 * kc + 1; o[2] = 3 * kc + 2; o[3] = 3 * kc + 2;
+    } else {
+      o[0] = 9; o[1] = 10; o[2] = 11; o[3] = 12;
+    }
+    int zs[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) zs[j] = h ? 6 + j : (j < 3 ? j : (j == 3 ? 0 : j - 1));
+    const double m3 = h ? 1.0 : 0.0;
+    double Kacc[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) Kacc[t] = 0.0;
+#pragma unroll 1
+    for (int gq = 0; gq < T::NQP; ++gq) {
+      const double jw = S.Jw[gq];
+      double w[4];
+      if (kc < 3) {
+        w[0] = S.G[gq][bnode][0]; w[1] = S.G[gq][bnode][1]; w[2] = S.G[gq][bnode][2]; w[3] = 0.0;
+      } else {
+        w[0] = S.N[gq][bnode]; w[1] = S.G[gq][bnode][0]; w[2] = S.G[gq][bnode][1]; w[3] = S.G[gq][bnode][2];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[i] *= jw;
+      double Tz[7];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const double* Dz = S.D[gq][zs[j]];
+        Tz[j] = Dz[o[0]] * w[0] + Dz[o[1]] * w[1] + Dz[o[2]] * w[2] + Dz[o[3]] * w[3];
+      }
+      Tz[3] *= m3;
+#pragma unroll
+      for (int an = 0; an < T::NEN; ++an) {
+        const double g0 = S.G[gq][an][0], g1 = S.G[gq][an][1], g2 = S.G[gq][an][2], nn = S.N[gq][an];
+        Kacc[2 * an] += g0 * Tz[0] + g1 * Tz[1] + g2 * Tz[2];
+        Kacc[2 * an + 1] += nn * Tz[3] + g0 * Tz[4] + g1 * Tz[5] + g2 * Tz[6];
+      }
+    }
+    // stage K_e in LDS (the D buffer is free now), then write the segments
+    double* Ke = &S.D[0][0][0];
+    wave_lds_sync();
+#pragma unroll
+    for (int an = 0; an < T::NEN; ++an) {
+      Ke[(an * 4 + 2 * h) * T::NDOFE + col] = Kacc[2 * an];
+      Ke[(an * 4 + 2 * h + 1) * T::NDOFE + col] = Kacc[2 * an + 1];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < SPL; ++t) {
+      const int sg = lane + 64 * t;
+      const int r = sg / T::NEN, bn = sg % T::NEN;
+      const d2_t* s2 = reinterpret_cast<const d2_t*>(Ke + r * T::NDOFE + bn * T::ND);
+      d2_t* k2 = reinterpret_cast<d2_t*>(a.K + soff[t]);
+      k2[0] = s2[0] + old0[t];
+      k2[1] = s2[1] + old1[t];
+    }
+  } else {
+    // Q4 (two elements per wavefront): lane owns one column and a block of rows
+    constexpr int RPL = 6;   // rows per lane
+    const int eslot = lane >> 5;
+    const int li = lane & 31;
     const int col = li % T::NDOFE;
     const int rb = (li / T::NDOFE) * RPL;
-    const bool own = (DIM == 3 ? true : li < 2 * T::NDOFE) && (slot_base + eslot < a.e_end);
+    const bool own = li < 2 * T::NDOFE && (slot_base + eslot < a.e_end);
     const int bnode = col / T::ND, kc = col % T::ND;
     double Kacc[RPL];
 #pragma unroll
@@ -700,55 +791,38 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
         Kacc[t] += jw * v;
       }
     }
-    // Stage K_e in LDS (the D buffer is free now), then write it one CSR
-    // block row segment (the ND columns of one element node) per lane: wide,
-    // mostly contiguous accesses.  The first colour that touches a block
-    // stores it, later colours read-modify-write it, so K needs no clearing.
+    // stage K_e in LDS (the D buffer is free now), then write it one CSR
+    // block-row segment (the ND columns of one element node) per lane; the
+    // first colour that touches a block stores it, later colours add to it
     double* Ke = &S.D[0][0][0] + eslot * T::NDOFE * T::NDOFE;
     wave_lds_sync();
     if (own) {
 #pragma unroll
       for (int t = 0; t < RPL; ++t) Ke[(rb + t) * T::NDOFE + col] = Kacc[t];
     }
-  }
-  wave_lds_sync();
-  {
+    wave_lds_sync();
     constexpr int NSEG = T::EPW * T::NDOFE * T::NEN;  // segments per wavefront
 #pragma unroll 1
     for (int sg = lane; sg < NSEG; sg += 64) {
       const int es = sg / (T::NDOFE * T::NEN);
       const int rem = sg - es * (T::NDOFE * T::NEN);
-      const int r = rem / T::NEN, bnode = rem % T::NEN;
+      const int r = rem / T::NEN, bn = rem % T::NEN;
       if (slot_base + es >= a.e_end) continue;
       const int ae = a.perm[slot_base + es];
       const int an = r / T::ND, cr = r % T::ND;
       const int nodea = a.conn[(long)ae * T::NEN + an];
-      const long off = (long)a.blk[((long)ae * T::NEN + an) * T::NEN + bnode] + (long)cr * a.rowstride[nodea];
-      const double* src = &S.D[0][0][0] + es * T::NDOFE * T::NDOFE + r * T::NDOFE + bnode * T::ND;
-      const bool first = (a.first[ae] >> (an * T::NEN + bnode)) & 1ull;
-      if constexpr (T::ND == 4) {
-        // 32-byte aligned segment (block rows start at multiples of 4 entries;
-        // the caller's K is 16-byte aligned)
-        const d2_t* s2 = reinterpret_cast<const d2_t*>(src);
-        d2_t* k2 = reinterpret_cast<d2_t*>(a.K + off);
-        d2_t v0 = s2[0], v1 = s2[1];
-        if (!first) {
-          v0 += k2[0];
-          v1 += k2[1];
-        }
-        k2[0] = v0;
-        k2[1] = v1;
-      } else {
-        double v[T::ND];
+      const long off = (long)a.blk[((long)ae * T::NEN + an) * T::NEN + bn] + (long)cr * a.rowstride[nodea];
+      const double* src = &S.D[0][0][0] + es * T::NDOFE * T::NDOFE + r * T::NDOFE + bn * T::ND;
+      const bool first = (a.first[ae] >> (an * T::NEN + bn)) & 1ull;
+      double v[T::ND];
 #pragma unroll
-        for (int k = 0; k < T::ND; ++k) v[k] = src[k];
-        if (!first) {
+      for (int k = 0; k < T::ND; ++k) v[k] = src[k];
+      if (!first) {
 #pragma unroll
-          for (int k = 0; k < T::ND; ++k) v[k] += a.K[off + k];
-        }
-#pragma unroll
-        for (int k = 0; k < T::ND; ++k) a.K[off + k] = v[k];
+        for (int k = 0; k < T::ND; ++k) v[k] += a.K[off + k];
       }
+#pragma unroll
+      for (int k = 0; k < T::ND; ++k) a.K[off + k] = v[k];
     }
   }
 }
