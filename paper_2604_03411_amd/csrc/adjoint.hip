@@ -230,7 +230,7 @@ __global__ __launch_bounds__(64) void adj_qp_kernel(AdjQpArgs a) {
     for (int r = 0; r < 9; ++r) psiF[r] = M.mu * (m0 * x1F[r] + m1 * x2F[r] + m2 * A[r]) + M.lam * pv1 * A[r];
     const double psi_e = M.mu * (jt[0] - a.n0 * x3) + M.lam * vol * vol;
     // history sensitivities at the converged kappa_n (Eqs. Gq_NN, dd_7)
-    const double f = exp_nonpos(-M.eta * fmax(kap - M.kd, 0.0));
+    const double f = exp_d(-M.eta * fmax(kap - M.kd, 0.0));
     const double fp = (kap > M.kd) ? -M.eta * f : 0.0;
     const double qk = psi_e + gb * (phi - kap) / (M.eta * f);
     double hk = -1.0, dNy = 0.0;

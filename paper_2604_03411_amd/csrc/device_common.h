@@ -40,7 +40,7 @@ __device__ __forceinline__ void shape_at(int a, int q, double& N, double dN[DIM]
 // ------------------------------------------------------------------ FP64 math
 // Elementary functions for the network activations, written for the argument
 // ranges the kernels use.
-//   exp(t), expm1(t) for t <= 0: Cody-Waite reduction t = n ln2 + r with
+//   exp(t), expm1(t) for t <= 700: Cody-Waite reduction t = n ln2 + r with
 //     |r| <= ln2/2 (ln2 split so that n * kLn2Hi is exact), Taylor series of
 //     expm1(r) through r^13/13! (truncation below 2^-60 relative), scaling by
 //     2^n; expm1 adds 2^n - 1, exact for the n that occur.
@@ -88,7 +88,7 @@ __device__ __forceinline__ double expm1_reduced(double t, double& n) {
   return fma(r * r, p, r);
 }
 
-__device__ __forceinline__ double exp_nonpos(double t) {
+__device__ __forceinline__ double exp_d(double t) {
   double n;
   const double q = expm1_reduced(t, n);
   return ldexp(1.0 + q, (int)n);
@@ -125,7 +125,7 @@ __device__ __forceinline__ double log1p_small(double y) {
 
 // softplus(a) and the logistic pair (s, 1 - s) at a.
 __device__ __forceinline__ double softplus_pair(double a, double& s, double& sb) {
-  const double e = exp_nonpos(-fabs(a));
+  const double e = exp_d(-fabs(a));
   const double inv = rcp_d(1.0 + e);
   s = (a >= 0.0) ? inv : e * inv;
   sb = (a >= 0.0) ? e * inv : inv;
@@ -202,7 +202,7 @@ __device__ __forceinline__ float delta_softplus(float d, float a0, float s0, flo
 
 // Plain softplus and logistic (yield network, evaluated directly).
 __device__ __forceinline__ double softplus_d(double a, double& s) {
-  const double e = exp_nonpos(-fabs(a));
+  const double e = exp_d(-fabs(a));
   const double inv = rcp_d(1.0 + e);
   s = (a >= 0.0) ? inv : e * inv;
   return fmax(a, 0.0) + log1p_small(e);

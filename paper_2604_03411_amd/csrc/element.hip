@@ -507,11 +507,11 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   const double kn = valid ? a.kappa_n[qg] : 0.0;
   double* sc = S.ysc[g];
   const double gb = M.gamma * M.beta;
+  const double gbe = gb / M.eta;  // q = psi_e + gbe (phi - kappa) / f_d(kappa)
   double kap = kn, dNy = 0.0;
   bool yielded = false;
   {
-    const double f0 = exp_nonpos(-M.eta * fmax(kn - M.kd, 0.0));
-    const double q0 = psi_e + gb * (phi - kn) / (M.eta * f0);
+    const double q0 = psi_e + gbe * (phi - kn) * exp_d(M.eta * fmax(kn - M.kd, 0.0));
     double d0;
     const double h0 = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, q0, sc, d0) - kn;
     dNy = d0;
@@ -542,13 +542,13 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
       // at least halves every second iteration even when h is dominated by
       // rounding near the root (there the Newton corrections are noise).
       double step1 = hi - lo, step2 = hi - lo;
+      double inv_f = exp_d(M.eta * fmax(k - M.kd, 0.0));  // 1 / f_d(k)
       for (int it = 0; it < a.max_local; ++it) {
         // Newton correction from the current iterate; the convergence test comes
         // before the bracket safeguard so that a root reached on the bracket's
         // end is accepted rather than bisected away from.
-        const double fk = exp_nonpos(-M.eta * fmax(k - M.kd, 0.0));
-        const double dq = gb / (M.eta * fk) * (-1.0 + ((k > M.kd) ? M.eta * (phi - k) : 0.0));
-        const double dk = -h / (dNy * dq - 1.0);
+        const double dq = gbe * inv_f * (-1.0 + ((k > M.kd) ? M.eta * (phi - k) : 0.0));
+        const double dk = div_d(-h, dNy * dq - 1.0);
         const double tol = 1e-15 * fmax(1.0, fabs(k));
         if (fabs(dk) <= tol) {
           k = fmin(fmax(k + dk, lo), hi);
@@ -564,8 +564,8 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
           step1 = fabs(dk);
         }
         k = kn1;
-        const double fk1 = exp_nonpos(-M.eta * fmax(k - M.kd, 0.0));
-        const double qk = psi_e + gb * (phi - k) / (M.eta * fk1);
+        inv_f = exp_d(M.eta * fmax(k - M.kd, 0.0));
+        const double qk = psi_e + gbe * (phi - k) * inv_f;
         h = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, qk, sc, dNy) - k;
         if (h > 0.0) lo = k; else hi = k;
         if (h == 0.0 || !(hi - lo > tol)) { conv = true; break; }
@@ -574,14 +574,15 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
       kap = k;
     }
   }
-  const double fkap = exp_nonpos(-M.eta * fmax(kap - M.kd, 0.0));
+  const double fkap = exp_d(-M.eta * fmax(kap - M.kd, 0.0));
   const double fpkap = (kap > M.kd) ? -M.eta * fkap : 0.0;
   double rhoF = 0.0, kphi = 0.0;
   if (yielded) {
-    const double dq = gb / (M.eta * fkap) * (-1.0 + ((kap > M.kd) ? M.eta * (phi - kap) : 0.0));
-    const double hk = dNy * dq - 1.0;
-    rhoF = -dNy / hk;
-    kphi = -dNy * gb / (M.eta * fkap) / hk;
+    const double inv_f = exp_d(M.eta * fmax(kap - M.kd, 0.0));
+    const double dq = gbe * inv_f * (-1.0 + ((kap > M.kd) ? M.eta * (phi - kap) : 0.0));
+    const double ihk = rcp_d(dNy * dq - 1.0);
+    rhoF = -dNy * ihk;
+    kphi = -dNy * gbe * inv_f * ihk;
   }
   if (TANGENT) {
     s.f = fkap; s.fp = fpkap; s.rhoF = rhoF; s.kphi = kphi;
