@@ -35,7 +35,10 @@ struct JetCfg {
   static constexpr int QP = QB + 2;        // padded activation row (doubles)
   static constexpr int Z_DBL = 4 * H * QP;
   static constexpr int X_DBL = QB * 3;
-  static constexpr int LDS_BYTES = 8 * (Z_DBL + X_DBL);
+  // backward-pass state of the middle layers 1 .. L-2 (logistic pair and the
+  // three input-Jacobian entries of each of a lane's 4 rows), lane-contiguous
+  static constexpr int ST_DBL = (L > 2 ? L - 2 : 0) * WAVES * 5 * 4 * 64;
+  static constexpr int LDS_BYTES = 8 * (Z_DBL + X_DBL + ST_DBL);
   static_assert(NT * QB * 10 <= Z_DBL, "reduction buffer aliases the activation buffer");
 };
 
@@ -46,6 +49,7 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
   extern __shared__ double lds[];
   double* Zs = lds;
   double* xs = Zs + C::Z_DBL;
+  double* st = xs + C::X_DBL;  // [layer-1][wave][field][row][lane]
   double* red = Zs;  // reused after the backward pass
   const NetLayout lay = make_layout_hd(3, H, L, 3);
   const double* __restrict__ net = a.net;
@@ -63,9 +67,17 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
     __syncthreads();
     const double x[3] = {xs[j * 3], xs[j * 3 + 1], xs[j * 3 + 2]};
 
-    double sS[L][4], sB[L][4];   // logistic pair at a_k, rows r of this lane
-    double Jt[L][4][3];          // da_k/dx for k >= 1 (layer 0: the rows of W0)
+    // Backward-pass state: layer 0's logistic pairs in registers (its input
+    // Jacobian is W0), layers 1 .. L-2 in this wave's LDS slice; the last
+    // hidden layer's adjoint is wz, known in the forward pass, so its Hessian
+    // term is added there and nothing of it is kept.
+    double s0r[4], sb0r[4];
     double dz[4], zt[4][3];
+    double part[10];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) part[t] = 0.0;
+    double abar[4];
+    const bool hess = a.with_hessian != 0;
 
     // layer 1: a_1 = W0 x + b0 (vector ALU)
 #pragma unroll
@@ -73,11 +85,26 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
       const int n = nt * 16 + lg + 4 * r;
       const double w0 = net[lay.W0 + n * 3], w1 = net[lay.W0 + n * 3 + 1], w2 = net[lay.W0 + n * 3 + 2];
       const double da = w0 * x[0] + w1 * x[1] + w2 * x[2];
-      dz[r] = delta_softplus(da, net[lay.a0 + n], net[lay.s0 + n], net[lay.sb0 + n],
-                                     sS[0][r], sB[0][r]);
-      zt[r][0] = sS[0][r] * w0;
-      zt[r][1] = sS[0][r] * w1;
-      zt[r][2] = sS[0][r] * w2;
+      dz[r] = delta_softplus(da, net[lay.a0 + n], net[lay.s0 + n], net[lay.sb0 + n], s0r[r], sb0r[r]);
+      zt[r][0] = s0r[r] * w0;
+      zt[r][1] = s0r[r] * w1;
+      zt[r][2] = s0r[r] * w2;
+      if (L == 1) {
+        const double wz = net[lay.wz + n];
+        part[0] += wz * dz[r];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
+        abar[r] = wz * s0r[r];
+        if (hess) {
+          const double c2 = abar[r] * sb0r[r];
+          part[4] += c2 * w0 * w0;
+          part[5] += c2 * w1 * w1;
+          part[6] += c2 * w2 * w2;
+          part[7] += c2 * w0 * w1;
+          part[8] += c2 * w0 * w2;
+          part[9] += c2 * w1 * w2;
+        }
+      }
     }
 
 #pragma unroll
@@ -103,74 +130,82 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
           acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Zs[c * H * QP + zb], acc[c], 0, 0, 0);
       }
       __syncthreads();
+      double* stk = st + ((size_t)(k - 1) * NT + nt) * 5 * 4 * 64 + lane;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int n = nt * 16 + lg + 4 * r;
         const double* wx = net + lay.Wx[k] + n * 3;
         const double da = acc[0][r] + wx[0] * x[0] + wx[1] * x[1] + wx[2] * x[2];
+        double jk[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) Jt[k][r][i] = acc[1 + i][r] + wx[i];
-        dz[r] = delta_softplus(da, net[lay.a0 + k * H + n], net[lay.s0 + k * H + n],
-                                       net[lay.sb0 + k * H + n],
-                                       sS[k][r], sB[k][r]);
+        for (int i = 0; i < 3; ++i) jk[i] = acc[1 + i][r] + wx[i];
+        double s_, sb_;
+        dz[r] = delta_softplus(da, net[lay.a0 + k * H + n], net[lay.s0 + k * H + n], net[lay.sb0 + k * H + n],
+                               s_, sb_);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) zt[r][i] = sS[k][r] * Jt[k][r][i];
+        for (int i = 0; i < 3; ++i) zt[r][i] = s_ * jk[i];
+        if (k == L - 1) {
+          const double wz = net[lay.wz + n];
+          part[0] += wz * dz[r];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
+          abar[r] = wz * s_;
+          if (hess) {
+            const double c2 = abar[r] * sb_;
+            part[4] += c2 * jk[0] * jk[0];
+            part[5] += c2 * jk[1] * jk[1];
+            part[6] += c2 * jk[2] * jk[2];
+            part[7] += c2 * jk[0] * jk[1];
+            part[8] += c2 * jk[0] * jk[2];
+            part[9] += c2 * jk[1] * jk[2];
+          }
+        } else if (hess) {
+          stk[(0 * 4 + r) * 64] = s_;
+          stk[(1 * 4 + r) * 64] = sb_;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) stk[((2 + i) * 4 + r) * 64] = jk[i];
+        }
       }
     }
 
-    // output layer partial sums over this lane's rows
-    double part[10];
+    if (hess) {
+      // zbar_{k-1} = W_k^T abar_k, then layer k-1's adjoint and Hessian term
 #pragma unroll
-    for (int t = 0; t < 10; ++t) part[t] = 0.0;
-    double zbar[4];
+      for (int k = L - 1; k >= 1; --k) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int n = nt * 16 + lg + 4 * r;
-      const double wz = net[lay.wz + n];
-      part[0] += wz * dz[r];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
-      zbar[r] = wz;
-    }
-
-    if (a.with_hessian) {
-#pragma unroll
-      for (int k = L - 1; k >= 0; --k) {
-        double abar[4];
+        for (int r = 0; r < 4; ++r) Zs[(nt * 16 + lg + 4 * r) * QP + j] = abar[r];
+        __syncthreads();
+        d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+        const double* Wt = wop + ((size_t)((k - 1) * 2 + 1) * NT + nt) * NS * 64 + lane;
+#pragma unroll 8
+        for (int s = 0; s < NS; ++s)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wt[s * 64], Zs[(4 * s + lg) * QP + li], acc, 0, 0, 0);
+        __syncthreads();
+        const double* stk = st + ((size_t)(k - 2) * NT + nt) * 5 * 4 * 64 + lane;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          abar[r] = zbar[r] * sS[k][r];
-          const double c2 = abar[r] * sB[k][r];
-          double Jr[3];
-          if (k == 0) {
+          double sv, sbv, Jr[3];
+          if (k - 1 == 0) {
             const int n = nt * 16 + lg + 4 * r;
+            sv = s0r[r];
+            sbv = sb0r[r];
             Jr[0] = net[lay.W0 + n * 3];
             Jr[1] = net[lay.W0 + n * 3 + 1];
             Jr[2] = net[lay.W0 + n * 3 + 2];
           } else {
-            Jr[0] = Jt[k][r][0];
-            Jr[1] = Jt[k][r][1];
-            Jr[2] = Jt[k][r][2];
+            sv = stk[(0 * 4 + r) * 64];
+            sbv = stk[(1 * 4 + r) * 64];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Jr[i] = stk[((2 + i) * 4 + r) * 64];
           }
+          abar[r] = acc[r] * sv;
+          const double c2 = abar[r] * sbv;
           part[4] += c2 * Jr[0] * Jr[0];
           part[5] += c2 * Jr[1] * Jr[1];
           part[6] += c2 * Jr[2] * Jr[2];
           part[7] += c2 * Jr[0] * Jr[1];
           part[8] += c2 * Jr[0] * Jr[2];
           part[9] += c2 * Jr[1] * Jr[2];
-        }
-        if (k > 0) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Zs[(nt * 16 + lg + 4 * r) * QP + j] = abar[r];
-          __syncthreads();
-          d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
-          const double* Wt = wop + ((size_t)((k - 1) * 2 + 1) * NT + nt) * NS * 64 + lane;
-#pragma unroll 8
-          for (int s = 0; s < NS; ++s)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wt[s * 64], Zs[(4 * s + lg) * QP + li], acc, 0, 0, 0);
-          __syncthreads();
-#pragma unroll
-          for (int r = 0; r < 4; ++r) zbar[r] = acc[r];
         }
       }
     }
