@@ -132,14 +132,6 @@ __device__ __forceinline__ double softplus_pair(double a, double& s, double& sb)
   return fmax(a, 0.0) + log1p_small(e);
 }
 
-__device__ __forceinline__ float softplus_pair(float a, float& s, float& sb) {
-  const float e = expf(-fabsf(a));
-  const float inv = 1.0f / (1.0f + e);
-  s = (a >= 0.0f) ? inv : e * inv;
-  sb = (a >= 0.0f) ? e * inv : inv;
-  return fmaxf(a, 0.0f) + log1pf(e);
-}
-
 // log(w) for w = 1 + y > 0, given both: y > -1/2 goes through the series in y
 // (relative precision of small y); otherwise w, which is then accurate, is
 // split as m 2^k with m in [3/4, 3/2) and log(w) = k ln2 + log1p(m - 1).
@@ -180,24 +172,28 @@ __device__ __forceinline__ double delta_softplus(double d, double a0, double s0,
   return (fa ? 0.0 : d) + log1p_pair(p * M, w);
 }
 
+// FP32 version for the mixed-precision jets (same forms, hardware exp / log /
+// reciprocal; expm1 and log1p of small arguments by their Taylor / atanh
+// series, so small increments keep relative precision).
 __device__ __forceinline__ float delta_softplus(float d, float a0, float s0, float sb0, float& s, float& sb) {
-  const bool neg = d <= 0.0f;
-  const float e = expm1f(neg ? d : -d);
-  const float y = (neg ? s0 : sb0) * e;
-  if (y > -0.5f) {
-    const float inv = 1.0f / (1.0f + y);
-    if (neg) {
-      s = s0 * (1.0f + e) * inv;
-      sb = sb0 * inv;
-      return log1pf(y);
-    }
-    s = s0 * inv;
-    sb = sb0 * (1.0f + e) * inv;
-    return d + log1pf(y);
-  }
-  float s_ref, sb_ref;
-  const float za = softplus_pair(a0 + d, s, sb);
-  return za - softplus_pair(a0, s_ref, sb_ref);
+  const bool fa = a0 + d <= 0.0f;
+  const float t = fa ? d : -d;
+  const float E = __expf(t);
+  const float Ms =
+      t * (1.0f + t * (0.5f + t * (1.0f / 6 + t * (1.0f / 24 + t * (1.0f / 120 + t * (1.0f / 720 + t * (1.0f / 5040)))))));
+  const float M = (fabsf(t) < 0.25f) ? Ms : E - 1.0f;
+  const float p = fa ? s0 : sb0, c = fa ? sb0 : s0;
+  const float w = fmaf(p, E, c);
+  const float inv = __builtin_amdgcn_rcpf(w);
+  const float sp = p * E * inv, sc = c * inv;
+  s = fa ? sp : sc;
+  sb = fa ? sc : sp;
+  const float y = p * M;
+  const float u = y * __builtin_amdgcn_rcpf(2.0f + y);
+  const float z = u * u;
+  const float Ls = 2.0f * u * (1.0f + z * (1.0f / 3 + z * (1.0f / 5 + z * (1.0f / 7 + z * (1.0f / 9)))));
+  const float Lg = (fabsf(y) < 0.25f) ? Ls : __logf(w);
+  return (fa ? 0.0f : d) + Lg;
 }
 
 // Plain softplus and logistic (yield network, evaluated directly).

@@ -106,7 +106,14 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
     __syncthreads();
     const float x[3] = {xs[j * 3], xs[j * 3 + 1], xs[j * 3 + 2]};
 
+    // State kept for the backward pass: layers 0 .. L-2 (the last hidden
+    // layer's adjoint is wz, so its Hessian term is added in the forward pass).
     float sS[L][4], sB[L][4], Jt[L][4][3], dz[4], zt[4][3];
+    float part[10];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) part[t] = 0.f;
+    float abar[4];
+    const bool hess = a.with_hessian != 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int n = nt * 16 + 4 * lg + r;
@@ -118,6 +125,22 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
       Jt[0][r][0] = w0; Jt[0][r][1] = w1; Jt[0][r][2] = w2;
 #pragma unroll
       for (int i = 0; i < 3; ++i) zt[r][i] = sS[0][r] * Jt[0][r][i];
+      if (L == 1) {
+        const float wz = (float)net[lay.wz + n];
+        part[0] += wz * dz[r];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
+        abar[r] = wz * sS[0][r];
+        if (hess) {
+          const float c2 = abar[r] * sB[0][r];
+          part[4] += c2 * w0 * w0;
+          part[5] += c2 * w1 * w1;
+          part[6] += c2 * w2 * w2;
+          part[7] += c2 * w0 * w1;
+          part[8] += c2 * w0 * w2;
+          part[9] += c2 * w1 * w2;
+        }
+      }
     }
 
 #pragma unroll
@@ -155,58 +178,61 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
         const double* wx = net + lay.Wx[k] + n * 3;
         const float wx0 = (float)wx[0], wx1 = (float)wx[1], wx2 = (float)wx[2];
         const float da = acc[0][r] + wx0 * x[0] + wx1 * x[1] + wx2 * x[2];
-        Jt[k][r][0] = acc[1][r] + wx0;
-        Jt[k][r][1] = acc[2][r] + wx1;
-        Jt[k][r][2] = acc[3][r] + wx2;
+        const float jk[3] = {acc[1][r] + wx0, acc[2][r] + wx1, acc[3][r] + wx2};
+        float s_, sb_;
         dz[r] = delta_softplus(da, (float)net[lay.a0 + k * H + n], (float)net[lay.s0 + k * H + n],
-                                      (float)net[lay.sb0 + k * H + n], sS[k][r], sB[k][r]);
+                                      (float)net[lay.sb0 + k * H + n], s_, sb_);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) zt[r][i] = sS[k][r] * Jt[k][r][i];
+        for (int i = 0; i < 3; ++i) zt[r][i] = s_ * jk[i];
+        if (k == L - 1) {
+          const float wz = (float)net[lay.wz + n];
+          part[0] += wz * dz[r];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
+          abar[r] = wz * s_;
+          if (hess) {
+            const float c2 = abar[r] * sb_;
+            part[4] += c2 * jk[0] * jk[0];
+            part[5] += c2 * jk[1] * jk[1];
+            part[6] += c2 * jk[2] * jk[2];
+            part[7] += c2 * jk[0] * jk[1];
+            part[8] += c2 * jk[0] * jk[2];
+            part[9] += c2 * jk[1] * jk[2];
+          }
+        } else {
+          sS[k][r] = s_;
+          sB[k][r] = sb_;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) Jt[k][r][i] = jk[i];
+        }
       }
     }
 
-    float part[10];
+    if (hess) {
 #pragma unroll
-    for (int t = 0; t < 10; ++t) part[t] = 0.f;
-    float zbar[4];
+      for (int k = L - 1; k >= 1; --k) {
+        V4 v;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float wz = (float)net[lay.wz + nt * 16 + 4 * lg + r];
-      part[0] += wz * dz[r];
+        for (int r = 0; r < 4; ++r) v[r] = (T)abar[r];
+        *reinterpret_cast<V4*>(&Zs[j * HP + nt * 16 + 4 * lg]) = v;
+        __syncthreads();
+        f4_t acc = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
-      zbar[r] = wz;
-    }
-    if (a.with_hessian) {
-#pragma unroll
-      for (int k = L - 1; k >= 0; --k) {
-        float abar[4];
+        for (int s = 0; s < KS; ++s)
+          acc = Lp<T>::mfma(Wb[k - 1][s], *reinterpret_cast<const V8*>(&Zs[(qt * 16 + li) * HP + 32 * s + 8 * lg]),
+                            acc);
+        __syncthreads();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          abar[r] = zbar[r] * sS[k][r];
-          const float c2 = abar[r] * sB[k][r];
-          const float* Jr = Jt[k][r];
+          abar[r] = acc[r] * sS[k - 1][r];
+          const float c2 = abar[r] * sB[k - 1][r];
+          const float* Jr = Jt[k - 1][r];
           part[4] += c2 * Jr[0] * Jr[0];
           part[5] += c2 * Jr[1] * Jr[1];
           part[6] += c2 * Jr[2] * Jr[2];
           part[7] += c2 * Jr[0] * Jr[1];
           part[8] += c2 * Jr[0] * Jr[2];
           part[9] += c2 * Jr[1] * Jr[2];
-        }
-        if (k > 0) {
-          V4 v;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] = (T)abar[r];
-          *reinterpret_cast<V4*>(&Zs[j * HP + nt * 16 + 4 * lg]) = v;
-          __syncthreads();
-          f4_t acc = f4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int s = 0; s < KS; ++s)
-            acc = Lp<T>::mfma(Wb[k - 1][s],
-                              *reinterpret_cast<const V8*>(&Zs[(qt * 16 + li) * HP + 32 * s + 8 * lg]), acc);
-          __syncthreads();
-#pragma unroll
-          for (int r = 0; r < 4; ++r) zbar[r] = acc[r];
         }
       }
     }
