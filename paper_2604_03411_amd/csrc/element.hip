@@ -664,18 +664,37 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     const int ae = a.perm[slot_base];
     // the segments this lane writes afterwards: issue their old values now,
     // so the loads complete while the tangent is integrated
+    // (index loads of all segments first, then the value loads: loads complete
+    // in order, so an index wait placed after a value load would wait for it)
     constexpr int SPL = T::NDOFE * T::NEN / 64;  // segments per lane
     long soff[SPL];
     bool sfirst[SPL];
     d2_t old0[SPL], old1[SPL];
+    int nodea_t[SPL], blk_t[SPL];
+    const uint64_t fbits = a.first[ae];
+#pragma unroll
+    for (int t = 0; t < SPL; ++t) {
+      const int sg = lane + 64 * t;
+      const int r = sg / T::NEN, bn = sg % T::NEN;
+      const int an = r / T::ND;
+      nodea_t[t] = a.conn[(long)ae * T::NEN + an];
+      blk_t[t] = a.blk[((long)ae * T::NEN + an) * T::NEN + bn];
+    }
 #pragma unroll
     for (int t = 0; t < SPL; ++t) {
       const int sg = lane + 64 * t;
       const int r = sg / T::NEN, bn = sg % T::NEN;
       const int an = r / T::ND, cr = r % T::ND;
-      const int nodea = a.conn[(long)ae * T::NEN + an];
-      soff[t] = (long)a.blk[((long)ae * T::NEN + an) * T::NEN + bn] + (long)cr * a.rowstride[nodea];
-      sfirst[t] = (a.first[ae] >> (an * T::NEN + bn)) & 1ull;
+      soff[t] = (long)blk_t[t] + (long)cr * a.rowstride[nodea_t[t]];
+      sfirst[t] = (fbits >> (an * T::NEN + bn)) & 1ull;
+    }
+    // Materialise every offset before the first value load (an empty asm that
+    // takes the offsets as operands), so no value load waits on index loads.
+#pragma unroll
+    for (int t = 0; t < SPL; ++t) asm volatile("" : "+v"(soff[t]));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < SPL; ++t) {
       old0[t] = d2_t{0.0, 0.0};
       old1[t] = d2_t{0.0, 0.0};
       if (!sfirst[t]) {
@@ -698,7 +717,7 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     double Kacc[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) Kacc[t] = 0.0;
-#pragma unroll 1
+#pragma unroll 2
     for (int gq = 0; gq < T::NQP; ++gq) {
       const double jw = S.Jw[gq];
       double w[4];
