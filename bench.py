@@ -41,7 +41,8 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
 PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 / FP16 matrix
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_energy_jet_fp64_hex8_64cube.txt")
-JET_SOURCE = os.path.join(ROOT, "paper_2604_03411_amd", "csrc", "icnn_jet.hip")
+JET_SOURCES = [os.path.join(ROOT, "paper_2604_03411_amd", "csrc", n)
+               for n in ("icnn_jet.hip", "device_common.h", "gedmg_internal.h")]
 
 
 def log(msg):
@@ -125,7 +126,8 @@ def bench_mixed(G, W, torch, ctx, fields, out, ref, steps, warmup, nq):
             f"tangent err {errs['tangent']:.2e}; converged-displacement check")
         errs.update(mixed_newton_error(G, W, torch, prec))
         res[prec] = dict(value=nq / (ms / steps * 1e-3), unit="qp/s", ms_per_step=ms / steps,
-                         jet_ms=per_call(prof, "jets"), element_ms=per_call(prof, "elements"),
+                         jet_ms=per_call(prof, "jets"), history_ms=per_call(prof, "history"),
+                         element_ms=per_call(prof, "elements"),
                          error_vs_fp64=errs)
     return res
 
@@ -181,12 +183,16 @@ def cpu_baseline(case, n_elems):
 
 def jet_traffic(launch_bytes_alg):
     """HBM bytes per jet launch from the committed rocprofv3 counter summary,
-    if it was taken on the current jet source; else None."""
+    if it was taken on the current jet sources (kernel, device math, argument
+    structs); else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
-        with open(JET_SOURCE, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for path in JET_SOURCES:
+            with open(path, "rb") as f:
+                h.update(f.read())
+        digest = h.hexdigest()
     except (OSError, ValueError, IndexError):
         return None
     if rec.get("jet_source_sha256") != digest:
@@ -243,15 +249,15 @@ def main():
     value = nq / (ms_step * 1e-3)
     H, L = case.energy.width, case.energy.n_hidden
     jet_ms, elem_ms = per_call(prof, "jets"), per_call(prof, "elements")
-    fill_ms, in_ms = per_call(prof, "fills"), per_call(prof, "inputs")
+    fill_ms, in_ms, hist_ms = per_call(prof, "fills"), per_call(prof, "inputs"), per_call(prof, "history")
     flops = jet_flops_per_qp(H, L) * nq
     jet_tf = flops / (jet_ms * 1e-3) / 1e12
     traffic = jet_traffic(nq * (3 + 10) * 8)
     roofline = dict(bound="mfma", achieved=round(jet_tf, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                     frac=round(jet_tf / PEAK_FP64_TFLOPS, 4), traffic=traffic, kernel="jet_f64_kernel",
                     flops_per_qp=jet_flops_per_qp(H, L), qp_per_launch=nq, ms_per_launch=round(jet_ms, 4))
-    log(f"{ms_step:.3f} ms/step; phases ms: inputs {in_ms:.3f} jets {jet_ms:.3f} elements {elem_ms:.3f} "
-        f"fills {fill_ms:.3f}")
+    log(f"{ms_step:.3f} ms/step; phases ms: inputs {in_ms:.3f} jets {jet_ms:.3f} history {hist_ms:.3f} "
+        f"elements {elem_ms:.3f} fills {fill_ms:.3f}")
 
     extra = {}
     if not args.no_mixed:
@@ -278,7 +284,7 @@ def main():
         config=dict(workload=case.name, elements=mesh.n_elems, qp=nq, dofs=int(mesh.ndof), nnz=int(ctx.nnz),
                     energy_net=f"3-{H}x{L}-1", yield_net=f"1-{case.yield_.width}x{case.yield_.n_hidden}-1",
                     precision="fp64"),
-        phases_ms=dict(inputs=in_ms, jets=jet_ms, elements=elem_ms, fills=fill_ms,
+        phases_ms=dict(inputs=in_ms, jets=jet_ms, history=hist_ms, elements=elem_ms, fills=fill_ms,
                        dominant="energy_jet" if jet_ms >= elem_ms else "element"),
         roofline=roofline, cpu_baseline=cpu, **extra)
     print(json.dumps(line), flush=True)

@@ -169,8 +169,9 @@ int gedmg_energy_jet(gedmg_ctx* ctx, const double* x, int64_t n, int precision, 
  * context's stream (for benchmarks).  enable != 0 starts recording and clears
  * the totals.  gedmg_profile_read synchronises and returns, in ms summed over
  * the assemblies since enabling: out[0] quadrature inputs, out[1] energy-
- * network jets, out[2] element kernels (all colours), out[3] zero fills;
- * *n_calls = assemblies timed.  out must hold 4 doubles (host). */
+ * network jets, out[2] local damage update, out[3] element kernels (all
+ * colours), out[4] zero fills; *n_calls = assemblies timed.  out must hold 5
+ * doubles (host). */
 int gedmg_profile(gedmg_ctx* ctx, int enable);
 int gedmg_profile_read(gedmg_ctx* ctx, double* out_ms, int32_t* n_calls);
 

@@ -1,13 +1,15 @@
-// Quadrature-point update, element residual / consistent tangent and the
-// atomic-free coloured scatter into CSR (Sec. 3.1 residual, Sec. 3.2 history
-// treatment of the monolithic scheme, Sec. 4.2 constitutive model).
+// Quadrature inputs, element residual / consistent tangent and the atomic-free
+// coloured scatter into CSR (Sec. 3.1 residual, Sec. 3.2 monolithic scheme,
+// Sec. 4.2 constitutive model).  The local damage update runs before the
+// element kernel, one lane per quadrature point; the element kernel takes the
+// updated history and its two sensitivities from there.
 //
 // One wavefront owns 8 quadrature points: one Hex8 element, or two Q4
 // elements.  Each quadrature point is served by a group of 8 lanes: the lanes
-// reduce the element gather, evaluate the yield network neuron-parallel and
-// split the consistent tangent's entries; the whole wavefront then integrates
-// K_e = sum_q Jw B^T D B column-parallel and writes its rows into CSR with
-// plain read-modify-write stores (elements of one colour share no node).
+// reduce the element gather and split the consistent tangent's rows; the whole
+// wavefront then integrates K_e = sum_q Jw B^T D B column-parallel and writes
+// its rows into CSR with plain stores, read-modify-write after the first
+// writer of a block (elements of one colour share no node).
 #include "device_common.h"
 #include "gedmg_internal.h"
 
@@ -44,11 +46,13 @@ __global__ __launch_bounds__(256) void qp_inputs_kernel(KinArgs a) {
   double Jx[DIM][DIM] = {};
   double dNs[T::NEN][DIM];
   int nodes[T::NEN];
+  double phiq = 0.0;
 #pragma unroll
   for (int n = 0; n < T::NEN; ++n) {
     nodes[n] = a.conn[(long)e * T::NEN + n];
     double Nv;
     shape_at<DIM>(n, q, Nv, dNs[n]);
+    phiq = fma(Nv, a.phi[nodes[n]], phiq);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const double xd = a.X[(long)d * a.n_nodes + nodes[n]];
@@ -116,67 +120,8 @@ __global__ __launch_bounds__(256) void qp_inputs_kernel(KinArgs a) {
   a.x[gid * 3 + 0] = I1 / (cj * cj) - 3.0;
   a.x[gid * 3 + 1] = I2 * I2 * I2 / (9.0 * J2 * J2) - 3.0;
   a.x[gid * 3 + 2] = J - 1.0;
+  a.phiq[gid] = phiq;
 }
-
-// ------------------------------------------------------------------ yield network
-// N^_kappa(q) and its derivative, neurons split over the 8 lanes of a group.
-// `sc` is this group's LDS scratch of 2*H doubles.
-template <int H>
-__device__ __forceinline__ double yield_eval_h(const double* __restrict__ net, int L, double yN0, int sub, double q,
-                               double* sc, double& dN) {
-  // offsets of the packed single-input network (see make_layout_hd), in closed form
-  constexpr int oW0 = 0, ob0 = H;
-  const int stride = H * H + 2 * H;             // Wz, Wx, b of one hidden layer
-  const int owz = 2 * H + (L - 1) * stride;
-  double pN = 0.0, pD = 0.0;
-  constexpr int per = H / 8;
-  double z[per], zt[per];
-#pragma unroll
-  for (int j = 0; j < per; ++j) {
-    const int n = sub + 8 * j;
-    const double w = net[oW0 + n];
-    double s;
-    z[j] = softplus_d(w * q + net[ob0 + n], s);
-    zt[j] = s * w;
-  }
-  for (int k = 1; k < L; ++k) {
-    wave_lds_sync();
-#pragma unroll
-    for (int j = 0; j < per; ++j) {
-      sc[sub + 8 * j] = z[j];
-      sc[H + sub + 8 * j] = zt[j];
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int j = 0; j < per; ++j) {
-      const int n = sub + 8 * j;
-      const int oWz = 2 * H + (k - 1) * stride, oWx = oWz + H * H, ob = oWx + H;
-      const double* Wz = net + oWz + n * H;
-      double acc = net[oWx + n] * q + net[ob + n];
-      double acct = net[oWx + n];
-      for (int m = 0; m < H; ++m) {
-        acc = fma(Wz[m], sc[m], acc);
-        acct = fma(Wz[m], sc[H + m], acct);
-      }
-      double s;
-      z[j] = softplus_d(acc, s);
-      zt[j] = s * acct;
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < per; ++j) {
-    const double w = net[owz + sub + 8 * j];
-    pN = fma(w, z[j], pN);
-    pD = fma(w, zt[j], pD);
-  }
-  pN = group8_sum(pN);
-  pD = group8_sum(pD);
-  const double wx = net[owz + H];
-  dN = pD + wx;
-  return pN + wx * q + net[owz + H + 1] - yN0;
-}
-
-
 
 // ------------------------------------------------------------------ per-qp state
 // Per-quadrature-point quantities the consistent tangent is built from (one
@@ -319,7 +264,7 @@ __device__ __forceinline__ void d_row(const Qp& __restrict__ s, const Material& 
 // ------------------------------------------------------------------ element kernel
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
-template <int DIM, int YH>
+template <int DIM>
 struct alignas(16) ElemLds {
   using T = Tr<DIM>;
   double G[8][T::NEN][3];  // grad N per qp
@@ -327,14 +272,13 @@ struct alignas(16) ElemLds {
   double Jw[8];
   double Pz[8][T::NZ];
   double D[8][T::NZ][T::NZ];
-  double ysc[8][2 * YH];   // yield-network scratch per group
   Qp qs[8];                // per-group state for the tangent rows
 };
 
-template <int DIM, bool TANGENT, int YH>
+template <int DIM, bool TANGENT>
 __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   using T = Tr<DIM>;
-  __shared__ ElemLds<DIM, YH> S;
+  __shared__ ElemLds<DIM> S;
   const int lane = threadIdx.x;
   const int g = lane >> 3, sub = lane & 7;
   const int es = (DIM == 3) ? 0 : (g >> 2);        // element slot of this group
@@ -503,87 +447,12 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     s.pv2 = 2.0 * (1.0 - iJ * iJ) * (1.0 - iJ * iJ) + 4.0 * vol * iJ * iJ * iJ;
   }
 
-  // ---------------- local history update (Eq. dd_7), safeguarded Newton
-  const double kn = valid ? a.kappa_n[qg] : 0.0;
-  double* sc = S.ysc[g];
-  const double gb = M.gamma * M.beta;
-  const double gbe = gb / M.eta;  // q = psi_e + gbe (phi - kappa) / f_d(kappa)
-  double kap = kn, dNy = 0.0;
-  bool yielded = false;
-  {
-    const double q0 = psi_e + gbe * (phi - kn) * exp_d(M.eta * fmax(kn - M.kd, 0.0));
-    double d0;
-    const double h0 = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, q0, sc, d0) - kn;
-    dNy = d0;
-    yielded = valid && (h0 > 0.0);
-    if (yielded) {
-      // Bracket [lo, hi] with h(lo) > 0 >= h(hi).  At kappa = phi the driving
-      // force is psi_e, so one evaluation gives both h(phi) = N^(psi_e) - phi
-      // and the bracket top max(kappa_n, phi, N^(psi_e)) (on which q <= psi_e).
-      // With a large penalty the root sits just above phi: start there when
-      // the yield condition still holds at phi.
-      double dtop;
-      const double top = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, psi_e, sc, dtop);
-      double lo = kn, hi = fmax(fmax(kn, phi), top);
-      double k = kn, h = h0;
-      if (phi > kn) {
-        if (top - phi > 0.0) {
-          lo = phi;
-          k = phi;
-          h = top - phi;
-          dNy = dtop;
-        } else {
-          hi = phi;
-        }
-      }
-      bool conv = false;
-      // Step sizes of the last two iterations: a Newton step longer than half
-      // the step before the last one is replaced by bisection, so the bracket
-      // at least halves every second iteration even when h is dominated by
-      // rounding near the root (there the Newton corrections are noise).
-      double step1 = hi - lo, step2 = hi - lo;
-      double inv_f = exp_d(M.eta * fmax(k - M.kd, 0.0));  // 1 / f_d(k)
-      for (int it = 0; it < a.max_local; ++it) {
-        // Newton correction from the current iterate; the convergence test comes
-        // before the bracket safeguard so that a root reached on the bracket's
-        // end is accepted rather than bisected away from.
-        const double dq = gbe * inv_f * (-1.0 + ((k > M.kd) ? M.eta * (phi - k) : 0.0));
-        const double dk = div_d(-h, dNy * dq - 1.0);
-        const double tol = 1e-15 * fmax(1.0, fabs(k));
-        if (fabs(dk) <= tol) {
-          k = fmin(fmax(k + dk, lo), hi);
-          conv = true;
-          break;
-        }
-        double kn1 = k + dk;
-        step2 = step1;
-        if (!(kn1 > lo && kn1 < hi) || 2.0 * fabs(dk) > step2) {
-          kn1 = 0.5 * (lo + hi);
-          step1 = 0.5 * (hi - lo);
-        } else {
-          step1 = fabs(dk);
-        }
-        k = kn1;
-        inv_f = exp_d(M.eta * fmax(k - M.kd, 0.0));
-        const double qk = psi_e + gbe * (phi - k) * inv_f;
-        h = yield_eval_h<YH>(a.ynet, a.yL, a.yN0, sub, qk, sc, dNy) - k;
-        if (h > 0.0) lo = k; else hi = k;
-        if (h == 0.0 || !(hi - lo > tol)) { conv = true; break; }
-      }
-      if (!conv) a.status[0] = GEDMG_E_LOCAL_NOCONV;
-      kap = k;
-    }
-  }
+  // ---------------- updated history (Eq. dd_7) and its sensitivities
+  const double kap = valid ? a.kappa[qg] : 0.0;
+  const d2_t sens = valid ? reinterpret_cast<const d2_t*>(a.sens)[qg] : d2_t{0.0, 0.0};
+  const double rhoF = sens[0], kphi = sens[1];
   const double fkap = exp_d(-M.eta * fmax(kap - M.kd, 0.0));
   const double fpkap = (kap > M.kd) ? -M.eta * fkap : 0.0;
-  double rhoF = 0.0, kphi = 0.0;
-  if (yielded) {
-    const double inv_f = exp_d(M.eta * fmax(kap - M.kd, 0.0));
-    const double dq = gbe * inv_f * (-1.0 + ((kap > M.kd) ? M.eta * (phi - kap) : 0.0));
-    const double ihk = rcp_d(dNy * dq - 1.0);
-    rhoF = -dNy * ihk;
-    kphi = -dNy * gbe * inv_f * ihk;
-  }
   if (TANGENT) {
     s.f = fkap; s.fp = fpkap; s.rhoF = rhoF; s.kphi = kphi;
   }
@@ -597,7 +466,6 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     S.Pz[g][DIM * DIM] = M.beta * (phi - kap);
 #pragma unroll
     for (int j = 0; j < DIM; ++j) S.Pz[g][DIM * DIM + 1 + j] = M.c * v[j];
-    if (valid) a.kappa_out[qg] = kap;
   }
   if (TANGENT) {
     // rows of D per lane: 3-D -> F rows 0..7 on lanes 0..7, F row 8 on lane 0
@@ -859,26 +727,17 @@ hipError_t launch_qp_inputs(int dim, const KinArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int DIM, bool TAN>
-static void launch_elem_t(const ElemArgs& a, int blocks, hipStream_t s) {
-  if (a.yH == 16)
-    hipLaunchKernelGGL((element_kernel<DIM, TAN, 16>), dim3(blocks), dim3(64), 0, s, a);
-  else
-    hipLaunchKernelGGL((element_kernel<DIM, TAN, 32>), dim3(blocks), dim3(64), 0, s, a);
-}
-
-hipError_t launch_element(int dim, bool tangent, const ElemArgs& a, int, hipStream_t s, int) {
-  if (a.yH != 16 && a.yH != 32) return hipErrorInvalidValue;
+hipError_t launch_element(int dim, bool tangent, const ElemArgs& a, hipStream_t s) {
   const int epw = dim == 3 ? 1 : 2;
   const int n = a.e_end - a.e_begin;
   const int blocks = (n + epw - 1) / epw;
   if (blocks == 0) return hipSuccess;
   if (dim == 3) {
-    if (tangent) launch_elem_t<3, true>(a, blocks, s);
-    else launch_elem_t<3, false>(a, blocks, s);
+    if (tangent) hipLaunchKernelGGL((element_kernel<3, true>), dim3(blocks), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((element_kernel<3, false>), dim3(blocks), dim3(64), 0, s, a);
   } else {
-    if (tangent) launch_elem_t<2, true>(a, blocks, s);
-    else launch_elem_t<2, false>(a, blocks, s);
+    if (tangent) hipLaunchKernelGGL((element_kernel<2, true>), dim3(blocks), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((element_kernel<2, false>), dim3(blocks), dim3(64), 0, s, a);
   }
   return hipGetLastError();
 }

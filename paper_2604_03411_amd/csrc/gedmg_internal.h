@@ -83,9 +83,29 @@ struct KinArgs {
   const double* X;       // [dim][n_nodes]
   const int32_t* conn;   // [n_elems][nen]
   const double* u;       // [dim][n_nodes]
+  const double* phi;     // [n_nodes]
   int n_nodes, n_elems;
   double* x;             // [n_elems*nqp][3]
+  double* phiq;          // [n_elems*nqp] phi interpolated at the point
   int* status;
+};
+
+// Arguments of the local damage update (one lane per quadrature point).
+struct HistArgs {
+  const double* x;       // [nq][3] network inputs; x[2] = J - 1
+  const double* jet;     // [nq][10]; jet[0] = N(x) - N(0)
+  const double* phiq;    // [nq]
+  const double* kappa_n; // [nq]
+  const double* ynet;    // packed yield network
+  double* kappa_out;     // [nq]
+  double* sens;          // [nq][2]: d kappa / d psi_e, d kappa / d phi
+  int* status;
+  long nq;
+  Material m;
+  double n0;             // energy network dN/dx3 at 0
+  double yN0;            // yield network N(0)
+  int yL;
+  int max_local;
 };
 
 struct ElemArgs {
@@ -97,27 +117,23 @@ struct ElemArgs {
   const uint64_t* first;     // [n_elems] bit a*nen+b: this element is the first (lowest colour) to write block (a,b)
   const double* u;
   const double* phi;
-  const double* kappa_n;
   const double* jet;         // [n_elems*nqp][10]
-  const double* ynet;        // packed yield network
+  const double* kappa;       // [n_elems*nqp] updated history (local update output)
+  const double* sens;        // [n_elems*nqp][2] its sensitivities to psi_e and phi
   double* R;
   double* K;                 // may be null (residual only)
-  double* kappa_out;
   int* status;
   int n_nodes, n_elems;
   int e_begin, e_end;        // range in perm of the colour being assembled
   Material m;
   double n0;                 // energy network dN/dx3 at 0
-  double yN0;                // yield network N(0)
-  int yH, yL;
-  int max_local;
 };
 
 // Kernel launchers (defined in the .hip translation units).
 hipError_t launch_qp_inputs(int dim, const KinArgs& a, hipStream_t s);
 hipError_t launch_energy_jet(int precision, int H, const JetArgs& a, hipStream_t s, int num_cu);
-hipError_t launch_element(int dim, bool tangent, const ElemArgs& a, int ynet_doubles,
-                          hipStream_t s, int num_cu);
+hipError_t launch_history(const HistArgs& a, int yH, hipStream_t s);
+hipError_t launch_element(int dim, bool tangent, const ElemArgs& a, hipStream_t s);
 void release_newton_work(gedmg_ctx* c);
 
 // Sparse helpers of the Newton driver, reused by the adjoint.
@@ -160,6 +176,8 @@ struct gedmg_ctx {
   double* dwop = nullptr;              // FP64 hidden weights in operand order (JetArgs::wop)
   double* dx = nullptr;                // [nq][3]
   double* djet = nullptr;              // [nq][10]
+  double* dphiq = nullptr;             // [nq]
+  double* dsens = nullptr;             // [nq][2]
   int* dstatus = nullptr;
   int max_local = 100;                 // history-update iteration limit
   // per-phase event profiling of gedmg_assemble

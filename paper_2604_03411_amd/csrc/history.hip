@@ -1,0 +1,178 @@
+// Local damage update (Sec. 3.2, Eq. dd_7): at every quadrature point the
+// history variable kappa solves h(kappa) = N^(q(kappa)) - kappa = 0 when the
+// trial state yields, with the driving force of Eqs. q_q_loc_q_nloc /
+// ostwald_potential,
+//   q(kappa) = psi_e + (gamma beta / eta) (phi - kappa) / f_d(kappa),
+// f_d(kappa) = exp(-eta <kappa - kappa_d>) (Eq. degradation_function), and
+// kappa = kappa_n otherwise.  The consistent tangent also needs the two
+// sensitivities of the solution, d kappa / d psi_e and d kappa / d phi.
+//
+// One lane per quadrature point: the inputs are per-point scalars (psi_e from
+// the energy jet and the invariant J - 1, phi interpolated by the quadrature-
+// input kernel, kappa_n), so the yield network (Eq. Gq_NN) is evaluated whole
+// in each lane and its neurons are independent instruction streams; the
+// weights are wave-uniform and come through the scalar cache.
+#include "device_common.h"
+#include "gedmg_internal.h"
+
+namespace gedmg {
+
+// N^(q) - N^(0) and dN^/dq of the packed single-input yield network (input-
+// convex layers with a skip connection from q, softplus activations).
+template <int H, int L>
+__device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net, double yN0, double q,
+                                                  double& dN) {
+  const int stride = H * H + 2 * H;  // Wz, Wx, b of one hidden layer
+  const int owz = 2 * H + (L - 1) * stride;
+  double z[H], zt[H];
+#pragma unroll
+  for (int n = 0; n < H; ++n) {
+    const double w = net[n];
+    double s;
+    z[n] = softplus_d(fma(w, q, net[H + n]), s);
+    zt[n] = s * w;
+  }
+#pragma unroll
+  for (int k = 1; k < L; ++k) {
+    const double* Wz = net + 2 * H + (k - 1) * stride;
+    const double* Wx = Wz + H * H;
+    const double* b = Wx + H;
+    double zn[H], ztn[H];
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+      double acc = fma(Wx[n], q, b[n]);
+      double acct = Wx[n];
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        acc = fma(Wz[n * H + m], z[m], acc);
+        acct = fma(Wz[n * H + m], zt[m], acct);
+      }
+      double s;
+      zn[n] = softplus_d(acc, s);
+      ztn[n] = s * acct;
+    }
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+      z[n] = zn[n];
+      zt[n] = ztn[n];
+    }
+  }
+  double pN = 0.0, pD = 0.0;
+#pragma unroll
+  for (int n = 0; n < H; ++n) {
+    pN = fma(net[owz + n], z[n], pN);
+    pD = fma(net[owz + n], zt[n], pD);
+  }
+  const double wx = net[owz + H];
+  dN = pD + wx;
+  return pN + wx * q + net[owz + H + 1] - yN0;
+}
+
+template <int YH, int YL>
+__global__ __launch_bounds__(256) void history_kernel(HistArgs a) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.nq) return;
+  const Material M = a.m;
+  // psi_e at the point (Eq. dd_0): mu (N(x) - N(0) - n0 x3) + lam (J + 1/J - 2)^2
+  const double x3 = a.x[g * 3 + 2];
+  const double Jd = 1.0 + x3;
+  const double vol = Jd + rcp_d(Jd) - 2.0;
+  const double psi_e = M.mu * (a.jet[g * 10] - a.n0 * x3) + M.lam * vol * vol;
+  const double phi = a.phiq[g];
+  const double kn = a.kappa_n[g];
+
+  const double gbe = M.gamma * M.beta / M.eta;  // q = psi_e + gbe (phi - kappa) / f_d(kappa)
+  double kap = kn, dNy = 0.0;
+  const double q0 = psi_e + gbe * (phi - kn) * exp_d(M.eta * fmax(kn - M.kd, 0.0));
+  double d0;
+  const double h0 = yield_eval_lane<YH, YL>(a.ynet, a.yN0, q0, d0) - kn;
+  dNy = d0;
+  const bool yielded = h0 > 0.0;
+  if (yielded) {
+    // Bracket [lo, hi] with h(lo) > 0 >= h(hi).  At kappa = phi the driving
+    // force is psi_e, so one evaluation gives both h(phi) = N^(psi_e) - phi and
+    // the bracket top max(kappa_n, phi, N^(psi_e)) (on which q <= psi_e).  With
+    // a large penalty the root sits just above phi: start there when the yield
+    // condition still holds at phi.
+    double dtop;
+    const double top = yield_eval_lane<YH, YL>(a.ynet, a.yN0, psi_e, dtop);
+    double lo = kn, hi = fmax(fmax(kn, phi), top);
+    double k = kn, h = h0;
+    if (phi > kn) {
+      if (top - phi > 0.0) {
+        lo = phi;
+        k = phi;
+        h = top - phi;
+        dNy = dtop;
+      } else {
+        hi = phi;
+      }
+    }
+    bool conv = false;
+    // Step sizes of the last two iterations: a Newton step longer than half the
+    // step before the last one is replaced by bisection, so the bracket at
+    // least halves every second iteration even when h is dominated by rounding
+    // near the root (there the Newton corrections are noise).
+    double step1 = hi - lo, step2 = hi - lo;
+    double inv_f = exp_d(M.eta * fmax(k - M.kd, 0.0));  // 1 / f_d(k)
+    for (int it = 0; it < a.max_local; ++it) {
+      // Newton correction from the current iterate; the convergence test comes
+      // before the bracket safeguard so that a root reached on the bracket's end
+      // is accepted rather than bisected away from.
+      const double dq = gbe * inv_f * (-1.0 + ((k > M.kd) ? M.eta * (phi - k) : 0.0));
+      const double dk = div_d(-h, dNy * dq - 1.0);
+      const double tol = 1e-15 * fmax(1.0, fabs(k));
+      if (fabs(dk) <= tol) {
+        k = fmin(fmax(k + dk, lo), hi);
+        conv = true;
+        break;
+      }
+      double kn1 = k + dk;
+      step2 = step1;
+      if (!(kn1 > lo && kn1 < hi) || 2.0 * fabs(dk) > step2) {
+        kn1 = 0.5 * (lo + hi);
+        step1 = 0.5 * (hi - lo);
+      } else {
+        step1 = fabs(dk);
+      }
+      k = kn1;
+      inv_f = exp_d(M.eta * fmax(k - M.kd, 0.0));
+      const double qk = psi_e + gbe * (phi - k) * inv_f;
+      h = yield_eval_lane<YH, YL>(a.ynet, a.yN0, qk, dNy) - k;
+      if (h > 0.0) lo = k; else hi = k;
+      if (h == 0.0 || !(hi - lo > tol)) { conv = true; break; }
+    }
+    if (!conv) a.status[0] = GEDMG_E_LOCAL_NOCONV;
+    kap = k;
+  }
+  // Sensitivities of the local solution (implicit function theorem on h = 0):
+  // d kappa / d psi_e = -N^' / h_kappa and d kappa / d phi = -N^' q_phi / h_kappa,
+  // with h_kappa = N^' q_kappa - 1; both vanish on the elastic branch.
+  double rhoF = 0.0, kphi = 0.0;
+  if (yielded) {
+    const double inv_f = exp_d(M.eta * fmax(kap - M.kd, 0.0));
+    const double dq = gbe * inv_f * (-1.0 + ((kap > M.kd) ? M.eta * (phi - kap) : 0.0));
+    const double ihk = rcp_d(dNy * dq - 1.0);
+    rhoF = -dNy * ihk;
+    kphi = -dNy * gbe * inv_f * ihk;
+  }
+  a.kappa_out[g] = kap;
+  a.sens[g * 2] = rhoF;
+  a.sens[g * 2 + 1] = kphi;
+}
+
+hipError_t launch_history(const HistArgs& a, int yH, hipStream_t s) {
+  const int blocks = (int)((a.nq + 255) / 256);
+  if (blocks == 0) return hipSuccess;
+  const dim3 g(blocks), b(256);
+  if (yH == 16 && a.yL == 1) hipLaunchKernelGGL((history_kernel<16, 1>), g, b, 0, s, a);
+  else if (yH == 16 && a.yL == 2) hipLaunchKernelGGL((history_kernel<16, 2>), g, b, 0, s, a);
+  else if (yH == 16 && a.yL == 3) hipLaunchKernelGGL((history_kernel<16, 3>), g, b, 0, s, a);
+  else if (yH == 32 && a.yL == 1) hipLaunchKernelGGL((history_kernel<32, 1>), g, b, 0, s, a);
+  else if (yH == 32 && a.yL == 2) hipLaunchKernelGGL((history_kernel<32, 2>), g, b, 0, s, a);
+  else if (yH == 32 && a.yL == 3) hipLaunchKernelGGL((history_kernel<32, 3>), g, b, 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace gedmg

@@ -162,7 +162,7 @@ int upload_params(gedmg_ctx* c, const double* te, const double* ty) {
 
 void free_all(gedmg_ctx* c) {
   void* ptrs[] = {c->dX, c->dconn, c->dperm, c->dblk, c->drowstride, c->dfirst, c->drowptr, c->dcol,
-                  c->denet, c->dynet, c->dw_bf16, c->dw_f16, c->dwop, c->dx, c->djet, c->dstatus};
+                  c->denet, c->dynet, c->dw_bf16, c->dw_f16, c->dwop, c->dx, c->djet, c->dphiq, c->dsens, c->dstatus};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -307,7 +307,8 @@ int gedmg_create(gedmg_ctx** out, const gedmg_mesh* mesh, const gedmg_material* 
       (rc = dalloc(c, &c->drowstride, nn)) || (rc = dalloc(c, &c->dfirst, (size_t)ne)) ||
       (rc = dalloc(c, &c->drowptr, rowptr.size())) ||
       (rc = dalloc(c, &c->dcol, nnz)) || (rc = dalloc(c, &c->dx, (size_t)nq * 3)) ||
-      (rc = dalloc(c, &c->djet, (size_t)nq * 10)) || (rc = dalloc(c, &c->dstatus, 4)))
+      (rc = dalloc(c, &c->djet, (size_t)nq * 10)) || (rc = dalloc(c, &c->dphiq, (size_t)nq)) ||
+      (rc = dalloc(c, &c->dsens, (size_t)nq * 2)) || (rc = dalloc(c, &c->dstatus, 4)))
     return fail(rc);
   GEDMG_HIP(c, hipMemcpy(c->dX, mesh->X, sizeof(double) * c->dim * nn, hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemcpy(c->dconn, conn, sizeof(int32_t) * ne * nen, hipMemcpyHostToDevice));
@@ -370,9 +371,10 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
     c->err = "K_vals must be 16-byte aligned";
     return GEDMG_E_ARG;
   }
-  hipEvent_t ev[5] = {};
+  constexpr int NEV = 6;
+  hipEvent_t ev[NEV] = {};
   if (c->prof) {
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < NEV; ++i) {
       GEDMG_HIP(c, hipEventCreate(&ev[i]));
       c->prof_ev.push_back(ev[i]);
     }
@@ -381,27 +383,31 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
   }
   GEDMG_HIP(c, hipMemsetAsync(R, 0, sizeof(double) * c->ndof, c->stream));
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[1], c->stream));
-  KinArgs ka{c->dX, c->dconn, u, c->n_nodes, c->n_elems, c->dx, c->dstatus};
+  KinArgs ka{c->dX, c->dconn, u, phi, c->n_nodes, c->n_elems, c->dx, c->dphiq, c->dstatus};
   GEDMG_HIP(c, launch_qp_inputs(c->dim, ka, c->stream));
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[2], c->stream));
+  const int64_t nq = (int64_t)c->n_elems * c->nqp;
   JetArgs ja{c->dx, c->djet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16, c->dwop,
-             (int)((int64_t)c->n_elems * c->nqp), c->elay.L, K_vals ? 1 : 0};
+             (int)nq, c->elay.L, K_vals ? 1 : 0};
   GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[3], c->stream));
+  HistArgs ha{c->dx, c->djet, c->dphiq, kappa_n, c->dynet, kappa_trial, c->dsens, c->dstatus, (long)nq,
+              c->mat, c->eref.n0, c->yref.N0, c->ylay.L, c->max_local};
+  GEDMG_HIP(c, launch_history(ha, c->ylay.H, c->stream));
+  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[4], c->stream));
   ElemArgs ea{};
   ea.X = c->dX; ea.conn = c->dconn; ea.perm = c->dperm; ea.blk = c->dblk; ea.rowstride = c->drowstride;
   ea.first = c->dfirst;
-  ea.u = u; ea.phi = phi; ea.kappa_n = kappa_n; ea.jet = c->djet; ea.ynet = c->dynet;
-  ea.R = R; ea.K = K_vals; ea.kappa_out = kappa_trial; ea.status = c->dstatus;
+  ea.u = u; ea.phi = phi; ea.jet = c->djet; ea.kappa = kappa_trial; ea.sens = c->dsens;
+  ea.R = R; ea.K = K_vals; ea.status = c->dstatus;
   ea.n_nodes = c->n_nodes; ea.n_elems = c->n_elems;
-  ea.m = c->mat; ea.n0 = c->eref.n0; ea.yN0 = c->yref.N0; ea.yH = c->ylay.H; ea.yL = c->ylay.L;
-  ea.max_local = c->max_local;
+  ea.m = c->mat; ea.n0 = c->eref.n0;
   for (size_t k = 0; k + 1 < c->color_begin.size(); ++k) {
     ea.e_begin = c->color_begin[k];
     ea.e_end = c->color_begin[k + 1];
-    GEDMG_HIP(c, launch_element(c->dim, K_vals != nullptr, ea, c->ylay.total, c->stream, c->num_cu));
+    GEDMG_HIP(c, launch_element(c->dim, K_vals != nullptr, ea, c->stream));
   }
-  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[4], c->stream));
+  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[5], c->stream));
   return GEDMG_OK;
 }
 
@@ -422,11 +428,11 @@ int gedmg_profile(gedmg_ctx* c, int enable) {
 int gedmg_profile_read(gedmg_ctx* c, double* out, int32_t* n_calls) {
   if (!c || !out) return GEDMG_E_ARG;
   GEDMG_HIP(c, hipStreamSynchronize(c->stream));
-  for (int i = 0; i < 4; ++i) out[i] = 0.0;
-  for (size_t b = 0; b + 4 < c->prof_ev.size() + 0 && b + 5 <= c->prof_ev.size(); b += 5) {
+  for (int i = 0; i < 5; ++i) out[i] = 0.0;
+  for (size_t b = 0; b + 6 <= c->prof_ev.size(); b += 6) {
     float ms;
-    const int map[4] = {1, 2, 3, 0};  // inputs, jets, elements, fills
-    for (int ph = 0; ph < 4; ++ph) {
+    const int map[5] = {1, 2, 3, 4, 0};  // inputs, jets, history, elements, fills
+    for (int ph = 0; ph < 5; ++ph) {
       const int i0 = map[ph];
       GEDMG_HIP(c, hipEventElapsedTime(&ms, c->prof_ev[b + i0], c->prof_ev[b + i0 + 1]));
       out[ph] += ms;

@@ -244,11 +244,12 @@ class Context:
         self._check(lib().gedmg_profile(self._h, 1 if enable else 0))
 
     def profile_read(self):
-        """Summed ms of (inputs, jets, elements, fills) and the number of timed assemblies."""
-        out = (C.c_double * 4)()
+        """Summed ms of (inputs, jets, history, elements, fills) and the number of timed assemblies."""
+        out = (C.c_double * 5)()
         n = C.c_int32()
         self._check(lib().gedmg_profile_read(self._h, out, C.byref(n)))
-        return dict(inputs=out[0], jets=out[1], elements=out[2], fills=out[3], calls=n.value)
+        return dict(inputs=out[0], jets=out[1], history=out[2], elements=out[3], fills=out[4],
+                    calls=n.value)
 
     def newton_step(self, u, phi, kappa, bc_dofs, bc_vals, precision="fp64", reaction_dofs=None,
                     max_newton=25, max_krylov=20000, max_local=100, newton_rtol=1e-10,
