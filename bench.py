@@ -42,7 +42,7 @@ PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 / FP16 matrix
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_energy_jet_fp64_hex8_64cube.txt")
 JET_SOURCES = [os.path.join(ROOT, "paper_2604_03411_amd", "csrc", n)
-               for n in ("icnn_jet.hip", "device_common.h", "gedmg_internal.h")]
+               for n in ("icnn_jet.hip", "device_common.h")]
 
 
 def log(msg):
@@ -183,8 +183,8 @@ def cpu_baseline(case, n_elems):
 
 def jet_traffic(launch_bytes_alg):
     """HBM bytes per jet launch from the committed rocprofv3 counter summary,
-    if it was taken on the current jet sources (kernel, device math, argument
-    structs); else None."""
+    if it was taken on the current jet sources (kernel and its device math);
+    else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
