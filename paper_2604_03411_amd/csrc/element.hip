@@ -136,6 +136,7 @@ struct Qp {
   double m[3];               // dN/dx - n0 e3
   double pv1, pv2;           // psi_vol', psi_vol''
   double f, fp, rhoF, kphi;  // f_d, f_d', d kappa/dF = rhoF psi_e,F, d kappa/d phi
+  double C[9], b[9], Ci[9];  // F^T F, F F^T, C^-1 (3-D rows only)
 };
 
 // Row r (3-D z index) of the consistent tangent D = dPz/dz (Pz = (P, dPsi/dphi,
@@ -259,6 +260,156 @@ __device__ __forceinline__ void d_row(const Qp& __restrict__ s, const Material& 
     }
     out[cz] = v;
   }
+}
+
+// Hex8 rows of D, the same quantities as d_row regrouped.  Every outer-product
+// part of D_FF lies in span{F, A, Q} (x1_F = a1 F + b1 A, x2_F = a2 Q + b2 A,
+// x3_F = A, psi_e,F = pF F + pA A + pQ Q), so with B_r = (F_r, A_r, Q_r)
+//   D_FF(r, c) = B_r S B_c^T + kA A_iL A_kJ + kF (F_iL F_kJ + d_ik C_JL + b_ik d_JL)
+//              + dd d_ik d_JL + w_k g1_L + v_L g2_k,       r = (i, J), c = (k, L),
+// with one symmetric 3x3 S per point (network Hessian term, the F/A/Q outer
+// products of J_FF, x1_FF, x2_FF, I2_FF and f_d' rhoF psi_e,F (x) psi_e,F),
+// g1_L = c_d (F^-1_Li v_J + w_i C^-1_JL) and g2_k = c_d w_i F^-1_Jk.  A lane
+// owns one row r; the row's slices of A, F, C, b and C^-1 come from LDS
+// (dynamic index), the column operands are compile-time register indices.
+// D_FF is symmetric, so row 8 of the F block is the transpose of column 8.
+struct HexRowCoef {
+  double S[3][3];
+  double kA, kF, dd, pF, pA, pQ, fpk, iJ, cd;
+};
+
+__device__ __forceinline__ HexRowCoef hex_row_coef(const Qp& __restrict__ s, const Material& M) {
+  HexRowCoef h;
+  const double iJ = 1.0 / s.J;
+  const double m0 = s.m[0], m1 = s.m[1], m2 = s.m[2];
+  const double I22 = s.I2 * s.I2, I23 = I22 * s.I2;
+  const double a1 = 2.0 * s.Jm23, b1 = -(2.0 / 3.0) * s.I1 * s.Jm53;
+  const double a2 = (1.0 / 3.0) * I22 * s.Jm4, b2 = -(4.0 / 9.0) * I23 * s.Jm5;
+  const double c_d1 = M.mu * m0 * a1;
+  const double c_FA = -M.mu * m0 * (4.0 / 3.0) * s.Jm53;
+  const double c_AA = M.mu * (m0 * (10.0 / 9.0) * s.I1 * s.Jm83 + m1 * (20.0 / 9.0) * I23 * s.Jm6) +
+                      M.lam * s.pv2;
+  const double c_J = M.mu * (-m0 * (2.0 / 3.0) * s.I1 * s.Jm53 - m1 * (4.0 / 9.0) * I23 * s.Jm5 + m2) +
+                     M.lam * s.pv1;
+  const double c_QQ = M.mu * m1 * (2.0 / 3.0) * s.I2 * s.Jm4;
+  const double c_QA = -M.mu * m1 * (4.0 / 3.0) * I22 * s.Jm5;
+  const double c_I2 = M.mu * m1 * (1.0 / 3.0) * I22 * s.Jm4;
+  // T: rows x1_F, x2_F, x3_F in the basis (F, A, Q); S1 = mu T^T Hn T
+  const double T[3][3] = {{a1, b1, 0.0}, {0.0, b2, a2}, {0.0, 1.0, 0.0}};
+  const double Hm[3][3] = {{s.Hn[0], s.Hn[3], s.Hn[4]}, {s.Hn[3], s.Hn[1], s.Hn[5]}, {s.Hn[4], s.Hn[5], s.Hn[2]}};
+  double HT[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) HT[a][b] = Hm[a][0] * T[0][b] + Hm[a][1] * T[1][b] + Hm[a][2] * T[2][b];
+  double S0[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) S0[a][b] = M.mu * (T[0][a] * HT[0][b] + T[1][a] * HT[1][b] + T[2][a] * HT[2][b]);
+  S0[0][0] += 4.0 * c_I2;
+  S0[0][1] += c_FA;
+  S0[1][0] += c_FA;
+  S0[1][1] += c_AA + c_J * iJ;
+  S0[1][2] += c_QA;
+  S0[2][1] += c_QA;
+  S0[2][2] += c_QQ;
+  h.pF = M.mu * m0 * a1;
+  h.pA = M.mu * (m0 * b1 + m1 * b2 + m2) + M.lam * s.pv1;
+  h.pQ = M.mu * m1 * a2;
+  const double p[3] = {h.pF, h.pA, h.pQ};
+  const double r1 = s.fp * s.rhoF;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) h.S[a][b] = s.f * S0[a][b] + r1 * p[a] * p[b];
+  h.kA = -s.f * c_J * iJ;
+  h.kF = -2.0 * s.f * c_I2;
+  h.dd = s.f * (c_d1 + 2.0 * c_I2 * s.I1);
+  h.fpk = s.fp * s.kphi;
+  h.iJ = iJ;
+  h.cd = M.c;
+  return h;
+}
+
+// F-block row r (0..8) of D for the F columns CB..8 and the phi / grad-phi
+// columns; with MIRROR the column-8 entry is also stored as D[8][r].
+template <int CB, bool MIRROR>
+__device__ __forceinline__ void hex_f_row(const Qp& __restrict__ s, const HexRowCoef& h, int r,
+                                          const double (&F)[9], const double (&A)[9], const double (&Q)[9],
+                                          const double (&w)[3], const double (&v)[3], double (*D)[13]) {
+  const int i = r / 3, J = r - 3 * (r / 3);
+  const double Fr = s.F[r], Ar = s.A[r], Qr = s.Q[r];
+  double Ai[3], AJ[3], Fi[3], FJ[3], CJ[3], bi[3], CiJ[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    Ai[t] = s.A[i * 3 + t];
+    AJ[t] = s.A[t * 3 + J];
+    Fi[t] = s.F[i * 3 + t];
+    FJ[t] = s.F[t * 3 + J];
+    CJ[t] = s.C[J * 3 + t];
+    bi[t] = s.b[i * 3 + t];
+    CiJ[t] = s.Ci[J * 3 + t];
+  }
+  const double wi = s.w[i], vJ = s.v[J];
+  double u[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) u[b] = Fr * h.S[0][b] + Ar * h.S[1][b] + Qr * h.S[2][b];
+  double rA[3], rF[3], rC[3], rb[3], g1[3], g2[3], dik[3], dJL[3];
+  const double cvJ = h.cd * vJ * h.iJ, cwi = h.cd * wi;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    rA[t] = h.kA * Ai[t];
+    rF[t] = h.kF * Fi[t];
+    rC[t] = h.kF * CJ[t];
+    rb[t] = h.kF * bi[t];
+    g1[t] = cvJ * Ai[t] + cwi * CiJ[t];
+    g2[t] = cwi * h.iJ * AJ[t];
+    dik[t] = (i == t) ? 1.0 : 0.0;
+    dJL[t] = (J == t) ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int c = CB; c < 9; ++c) {
+    const int k = c / 3, L = c % 3;
+    double x = u[0] * F[c] + u[1] * A[c] + u[2] * Q[c];
+    x += rA[L] * AJ[k] + rF[L] * FJ[k];
+    x += dik[k] * (rC[L] + dJL[L] * h.dd) + dJL[L] * rb[k];
+    x += w[k] * g1[L] + v[L] * g2[k];
+    D[r][c] = x;
+    if (MIRROR && c == 8) D[8][r] = x;
+  }
+  D[r][9] = h.fpk * (h.pF * Fr + h.pA * Ar + h.pQ * Qr);
+#pragma unroll
+  for (int L = 0; L < 3; ++L) D[r][10 + L] = -g1[L];
+}
+
+// phi row (r = 9) and grad-phi rows (r = 10..12) in one form, so the four
+// lanes run without divergence:
+//   D(r, c) = al . (F_c, A_c, Q_c) + be_k v_L + w_k ga_L   (F columns c = (k, L))
+// phi row: al = -beta rhoF psi_e,F coefficients, be = ga = 0;
+// grad row Jp: al = 0, be_k = -c_d F^-1_{Jp k}, ga_L = -c_d C^-1_{L Jp}.
+__device__ __forceinline__ void hex_pg_row(const Qp& __restrict__ s, const Material& M, const HexRowCoef& h,
+                                           int r, const double (&F)[9], const double (&A)[9],
+                                           const double (&Q)[9], const double (&w)[3], const double (&v)[3],
+                                           double (*D)[13]) {
+  const bool pr = r == 9;
+  const int Jp = pr ? 0 : r - 10;
+  const double bk = -M.beta * s.rhoF;
+  const double al0 = pr ? bk * h.pF : 0.0, al1 = pr ? bk * h.pA : 0.0, al2 = pr ? bk * h.pQ : 0.0;
+  double be[3], ga[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    be[t] = pr ? 0.0 : -h.cd * h.iJ * s.A[t * 3 + Jp];
+    ga[t] = pr ? 0.0 : s.Ci[Jp * 3 + t];
+  }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const int k = c / 3, L = c % 3;
+    D[r][c] = al0 * F[c] + al1 * A[c] + al2 * Q[c] + be[k] * v[L] - h.cd * w[k] * ga[L];
+  }
+  D[r][9] = pr ? M.beta * (1.0 - s.kphi) : 0.0;
+#pragma unroll
+  for (int L = 0; L < 3; ++L) D[r][10 + L] = pr ? 0.0 : h.cd * ga[L];
 }
 
 // ------------------------------------------------------------------ element kernel
@@ -445,6 +596,16 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     s.m[0] = m0; s.m[1] = m1; s.m[2] = m2;
     s.pv1 = pv1;
     s.pv2 = 2.0 * (1.0 - iJ * iJ) * (1.0 - iJ * iJ) + 4.0 * vol * iJ * iJ * iJ;
+    if constexpr (DIM == 3) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          s.C[i * 3 + j] = C[i * 3 + j];
+          s.b[i * 3 + j] = F[i * 3] * F[j * 3] + F[i * 3 + 1] * F[j * 3 + 1] + F[i * 3 + 2] * F[j * 3 + 2];
+          s.Ci[i * 3 + j] = (A[i] * A[j] + A[3 + i] * A[3 + j] + A[6 + i] * A[6 + j]) * iJ * iJ;
+        }
+    }
   }
 
   // ---------------- updated history (Eq. dd_7) and its sensitivities
@@ -468,20 +629,35 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     for (int j = 0; j < DIM; ++j) S.Pz[g][DIM * DIM + 1 + j] = M.c * v[j];
   }
   if (TANGENT) {
-    // rows of D per lane: 3-D -> F rows 0..7 on lanes 0..7, F row 8 on lane 0
-    // and the phi / grad-phi rows 9..12 on lanes 1..4; 2-D -> row sub (< 7)
     wave_lds_sync();
-    double dr[T::NZ];
-    if (sub < T::NZ) {
-      d_row<DIM>(S.qs[g], M, z3<DIM>(sub), dr);
+    if constexpr (DIM == 3) {
+      // F rows 0..7 on lanes 0..7 (column 8 mirrored into row 8); then row 8's
+      // remaining entries on lane 0 and the phi / grad-phi rows 9..12 on lanes 1..4
+      const Qp& sq = S.qs[g];
+      const HexRowCoef h = hex_row_coef(sq, M);
+      double Fc[9], Ac[9], Qc[9], wc[3], vc[3];
 #pragma unroll
-      for (int c = 0; c < T::NZ; ++c) S.D[g][sub][c] = dr[c];
-    }
-    if (DIM == 3 && sub <= 4) {
-      const int r1 = 8 + sub + (sub == 0 ? 0 : 0);
-      d_row<DIM>(S.qs[g], M, z3<DIM>(r1), dr);
+      for (int t = 0; t < 9; ++t) {
+        Fc[t] = sq.F[t];
+        Ac[t] = sq.A[t];
+        Qc[t] = sq.Q[t];
+      }
 #pragma unroll
-      for (int c = 0; c < T::NZ; ++c) S.D[g][r1][c] = dr[c];
+      for (int t = 0; t < 3; ++t) {
+        wc[t] = sq.w[t];
+        vc[t] = sq.v[t];
+      }
+      hex_f_row<0, true>(sq, h, sub, Fc, Ac, Qc, wc, vc, S.D[g]);
+      if (sub == 0) hex_f_row<8, false>(sq, h, 8, Fc, Ac, Qc, wc, vc, S.D[g]);
+      else if (sub <= 4) hex_pg_row(sq, M, h, 8 + sub, Fc, Ac, Qc, wc, vc, S.D[g]);
+    } else {
+      // 2-D: row sub (< 7) per lane
+      double dr[T::NZ];
+      if (sub < T::NZ) {
+        d_row<DIM>(S.qs[g], M, z3<DIM>(sub), dr);
+#pragma unroll
+        for (int c = 0; c < T::NZ; ++c) S.D[g][sub][c] = dr[c];
+      }
     }
   }
   __syncthreads();
