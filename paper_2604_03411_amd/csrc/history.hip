@@ -68,6 +68,66 @@ __device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net
   return pN + wx * q + net[owz + H + 1] - yN0;
 }
 
+// The same network in FP32 with the hardware exponential, logarithm and
+// reciprocal (relative error about 1e-6): the model the FP32 pre-solve iterates on.
+template <int H, int L>
+__device__ __forceinline__ float yield_eval_lane_f32(const double* __restrict__ net, float yN0, float q,
+                                                     float& dN) {
+  const int stride = H * H + 2 * H;
+  const int owz = 2 * H + (L - 1) * stride;
+  auto sp = [](float t, float& s) {
+    const float e = __expf(-fabsf(t));
+    const float inv = __builtin_amdgcn_rcpf(1.0f + e);
+    s = (t >= 0.0f) ? inv : e * inv;
+    return fmaxf(t, 0.0f) + __logf(1.0f + e);
+  };
+  float z[H], zt[H];
+#pragma unroll
+  for (int n = 0; n < H; ++n) {
+    const float w = (float)net[n];
+    float s;
+    z[n] = sp(fmaf(w, q, (float)net[H + n]), s);
+    zt[n] = s * w;
+  }
+#pragma unroll
+  for (int k = 1; k < L; ++k) {
+    const double* Wz = net + 2 * H + (k - 1) * stride;
+    const double* Wx = Wz + H * H;
+    const double* b = Wx + H;
+    float zn[H], ztn[H];
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+      float acc = fmaf((float)Wx[n], q, (float)b[n]);
+      float acct = (float)Wx[n];
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        acc = fmaf((float)Wz[n * H + m], z[m], acc);
+        acct = fmaf((float)Wz[n * H + m], zt[m], acct);
+      }
+      float s;
+      zn[n] = sp(acc, s);
+      ztn[n] = s * acct;
+    }
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+      z[n] = zn[n];
+      zt[n] = ztn[n];
+    }
+  }
+  float pN = 0.0f, pD = 0.0f;
+#pragma unroll
+  for (int n = 0; n < H; ++n) {
+    pN = fmaf((float)net[owz + n], z[n], pN);
+    pD = fmaf((float)net[owz + n], zt[n], pD);
+  }
+  const float wx = (float)net[owz + H];
+  dN = pD + wx;
+  return pN + wx * q + (float)net[owz + H + 1] - yN0;
+}
+
+// FP32 pre-solve iterations (not counted against max_local).
+constexpr int kF32Iters = 12;
+
 template <int YH, int YL>
 __global__ __launch_bounds__(256) void history_kernel(HistArgs a) {
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -89,23 +149,58 @@ __global__ __launch_bounds__(256) void history_kernel(HistArgs a) {
   dNy = d0;
   const bool yielded = h0 > 0.0;
   if (yielded) {
-    // Bracket [lo, hi] with h(lo) > 0 >= h(hi).  At kappa = phi the driving
-    // force is psi_e, so one evaluation gives both h(phi) = N^(psi_e) - phi and
-    // the bracket top max(kappa_n, phi, N^(psi_e)) (on which q <= psi_e).  With
-    // a large penalty the root sits just above phi: start there when the yield
-    // condition still holds at phi.
-    double dtop;
-    const double top = yield_eval_lane<YH, YL>(a.ynet, a.yN0, psi_e, dtop);
-    double lo = kn, hi = fmax(fmax(kn, phi), top);
-    double k = kn, h = h0;
-    if (phi > kn) {
-      if (top - phi > 0.0) {
-        lo = phi;
-        k = phi;
-        h = top - phi;
-        dNy = dtop;
-      } else {
-        hi = phi;
+    // Bracket [lo, hi] with h(lo) > 0 >= h(hi): h(kappa_n) = h0 > 0, and on
+    // kappa >= phi the driving force is at most psi_e, so h <= N^(psi_e) - kappa
+    // there and any top >= max(kappa_n, phi, N^(psi_e)) closes the bracket.
+    double lo = kn, hi, k = kn, h = h0;
+    if constexpr (YL == 1) {
+      // Single hidden layer: N^(psi_e) from the FP32 network with a margin far
+      // above its error, and the root first located by safeguarded Newton on the
+      // FP32 model; the FP64 iteration below starts there and decides convergence.
+      const float psif = (float)psi_e, phif = (float)phi, gbef = (float)gbe;
+      const float etaf = (float)M.eta, kdf = (float)M.kd, yN0f = (float)a.yN0;
+      float dtopf;
+      const float topf = yield_eval_lane_f32<YH, YL>(a.ynet, yN0f, psif, dtopf);
+      const double top = (double)topf + 1e-4 * (1.0 + fabs((double)topf));
+      hi = fmax(fmax(kn, phi), top);
+      float lof = (float)lo, hif = (float)hi, kf = (float)kn;
+      for (int it = 0; it < kF32Iters; ++it) {
+        const float invf = __expf(fminf(etaf * fmaxf(kf - kdf, 0.0f), 80.0f));
+        const float qf = psif + gbef * (phif - kf) * invf;
+        float dNf;
+        const float hf = yield_eval_lane_f32<YH, YL>(a.ynet, yN0f, qf, dNf) - kf;
+        if (hf > 0.0f) lof = kf; else hif = kf;
+        const float dqf = gbef * invf * (-1.0f + ((kf > kdf) ? etaf * (phif - kf) : 0.0f));
+        float kn1 = kf - hf * __builtin_amdgcn_rcpf(dNf * dqf - 1.0f);
+        if (!(kn1 > lof && kn1 < hif)) kn1 = 0.5f * (lof + hif);
+        const bool done = fabsf(kn1 - kf) <= 1e-6f * fmaxf(1.0f, fabsf(kf));
+        kf = kn1;
+        if (done) break;
+      }
+      const double ks = (double)kf;
+      if (ks > lo && ks < hi) {
+        k = ks;
+        const double qk = psi_e + gbe * (phi - k) * exp_d(M.eta * fmax(k - M.kd, 0.0));
+        h = yield_eval_lane<YH, YL>(a.ynet, a.yN0, qk, dNy) - k;
+        if (h > 0.0) lo = k; else hi = k;
+      }
+    } else {
+      // At kappa = phi the driving force is psi_e, so one evaluation gives both
+      // h(phi) = N^(psi_e) - phi and the bracket top; with a large penalty the
+      // root sits just above phi: start there when the yield condition still
+      // holds at phi.
+      double dtop;
+      const double top = yield_eval_lane<YH, YL>(a.ynet, a.yN0, psi_e, dtop);
+      hi = fmax(fmax(kn, phi), top);
+      if (phi > kn) {
+        if (top - phi > 0.0) {
+          lo = phi;
+          k = phi;
+          h = top - phi;
+          dNy = dtop;
+        } else {
+          hi = phi;
+        }
       }
     }
     bool conv = false;
