@@ -439,13 +439,26 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   const bool valid = pe < a.e_end;
   const int e = valid ? a.perm[pe] : 0;
   const Material M = a.m;
+  const long qg = (long)e * T::NQP + q;
 
   // ---------------- gather and kinematics (lane sub serves node sub)
   const bool has_node = valid && sub < T::NEN;
   int node = 0;
+  if (has_node) node = a.conn[(long)e * T::NEN + sub];
+  // Loads that do not depend on the connectivity, issued before the gather
+  // chain so that their latency overlaps it: this point's jet row, updated
+  // history and its sensitivities.
+  d2_t jv[5] = {}, sens = {};
+  double kap = 0.0;
+  if (valid) {
+    const d2_t* jr = reinterpret_cast<const d2_t*>(a.jet + qg * 10);
+#pragma unroll
+    for (int t = 0; t < 5; ++t) jv[t] = jr[t];
+    kap = a.kappa[qg];
+    sens = reinterpret_cast<const d2_t*>(a.sens)[qg];
+  }
   double Xn[DIM] = {}, un[DIM] = {}, phin = 0.0, Nv = 0.0, dN[DIM] = {};
   if (has_node) {
-    node = a.conn[(long)e * T::NEN + sub];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       Xn[d] = a.X[(long)d * a.n_nodes + node];
@@ -454,6 +467,15 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     phin = a.phi[node];
     shape_at<DIM>(sub, q, Nv, dN);
   }
+  // The residual entries this wave updates at the end (lane dl owns element
+  // dof dl: node dl / ND, component dl % ND); the node comes from the lane of
+  // the first group of the element slot that gathered it.
+  const int r_slot = (DIM == 3) ? 0 : (lane >> 5);
+  const int r_dl = (DIM == 3) ? lane : (lane & 31);
+  const bool r_own = r_dl < T::NDOFE && (slot_base + r_slot < a.e_end);
+  const int r_node = __shfl(node, r_slot * 32 + r_dl / T::ND, 64);
+  const long r_idx = (long)r_node * T::ND + r_dl % T::ND;
+  const double r_old = r_own ? a.R[r_idx] : 0.0;
   double Jx[DIM][DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d)
@@ -564,8 +586,8 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   for (int i = 0; i < 3; ++i) w[i] = F[i * 3] * v[0] + F[i * 3 + 1] * v[1] + F[i * 3 + 2] * v[2];
 
   // ---------------- energy from the network jet
-  const long qg = (long)e * T::NQP + q;
-  const double* jt = a.jet + qg * 10;
+  const double jt[10] = {jv[0][0], jv[0][1], jv[1][0], jv[1][1], jv[2][0],
+                         jv[2][1], jv[3][0], jv[3][1], jv[4][0], jv[4][1]};
   const double dNx = jt[0];
   const double m0 = jt[1], m1 = jt[2], m2 = jt[3] - a.n0;
   const double vol = Jd + iJ - 2.0;
@@ -609,8 +631,6 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   }
 
   // ---------------- updated history (Eq. dd_7) and its sensitivities
-  const double kap = valid ? a.kappa[qg] : 0.0;
-  const d2_t sens = valid ? reinterpret_cast<const d2_t*>(a.sens)[qg] : d2_t{0.0, 0.0};
   const double rhoF = sens[0], kphi = sens[1];
   const double fkap = exp_d(-M.eta * fmax(kap - M.kd, 0.0));
   const double fpkap = (kap > M.kd) ? -M.eta * fkap : 0.0;
@@ -664,12 +684,9 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
 
   // ---------------- element residual: lanes own element dofs
   {
-    const int eslot = (DIM == 3) ? 0 : (lane >> 5);
-    const int dl = (DIM == 3) ? lane : (lane & 31);
-    const bool own = (DIM == 3 ? lane < T::NDOFE : dl < T::NDOFE) &&
-                     (slot_base + eslot < a.e_end);
-    if (own) {
-      const int ae = a.perm[slot_base + eslot];
+    const int eslot = r_slot;
+    const int dl = r_dl;
+    if (r_own) {
       const int an = dl / T::ND, cc = dl % T::ND;
       double acc = 0.0;
 #pragma unroll 1
@@ -688,8 +705,7 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
         }
         acc += S.Jw[gq] * t;
       }
-      const int nodea = a.conn[(long)ae * T::NEN + an];
-      a.R[(long)nodea * T::ND + cc] += acc;
+      a.R[r_idx] = r_old + acc;
     }
   }
   if (!TANGENT) return;
