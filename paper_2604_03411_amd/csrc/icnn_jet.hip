@@ -32,13 +32,17 @@ struct JetCfg {
   static constexpr int NT = H / 16;        // neuron tiles = waves per block
   static constexpr int WAVES = NT;
   static constexpr int QB = 16;            // quadrature points per batch
-  static constexpr int QP = QB + 2;        // padded activation row (doubles)
+  static constexpr int QP = QB;            // activation row (doubles)
   static constexpr int Z_DBL = 4 * H * QP;
   static constexpr int X_DBL = QB * 3;
   // backward-pass state of the middle layers 1 .. L-2 (logistic pair and the
   // three input-Jacobian entries of each of a lane's 4 rows), lane-contiguous
   static constexpr int ST_DBL = (L > 2 ? L - 2 : 0) * WAVES * 5 * 4 * 64;
-  static constexpr int LDS_BYTES = 8 * (Z_DBL + X_DBL + ST_DBL);
+  // per-neuron constants of the hidden->hidden layers 1 .. L-1 (a0, s0, sb0 and
+  // the three input weights Wx), then the output weights wz; staged once per
+  // block so the activation phases read them from LDS instead of memory
+  static constexpr int C_DBL = (L - 1) * 6 * H + H;
+  static constexpr int LDS_BYTES = 8 * (Z_DBL + X_DBL + ST_DBL + C_DBL);
   static_assert(NT * QB * 10 <= Z_DBL, "reduction buffer aliases the activation buffer");
 };
 
@@ -50,6 +54,7 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
   double* Zs = lds;
   double* xs = Zs + C::Z_DBL;
   double* st = xs + C::X_DBL;  // [layer-1][wave][field][row][lane]
+  double* cst = st + C::ST_DBL;  // [layer-1][a0, s0, sb0, wx0, wx1, wx2][neuron], then wz[neuron]
   double* red = Zs;  // reused after the backward pass
   const NetLayout lay = make_layout_hd(3, H, L, 3);
   const double* __restrict__ net = a.net;
@@ -59,6 +64,19 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
   const int li = lane & 15, lg = lane >> 4;
   const int j = li;  // qp column in the batch
   const int nbatch = (a.nq + QB - 1) / QB;
+  for (int idx = threadIdx.x; idx < C::C_DBL; idx += blockDim.x) {
+    double v;
+    if (idx < (L - 1) * 6 * H) {
+      const int k = 1 + idx / (6 * H), f = (idx / H) % 6, n = idx % H;
+      v = f == 0 ? net[lay.a0 + k * H + n]
+        : f == 1 ? net[lay.s0 + k * H + n]
+        : f == 2 ? net[lay.sb0 + k * H + n]
+                 : net[lay.Wx[k] + n * 3 + (f - 3)];
+    } else {
+      v = net[lay.wz + idx - (L - 1) * 6 * H];
+    }
+    cst[idx] = v;
+  }
 
   for (int batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
     const long q0 = (long)batch * QB;
@@ -134,18 +152,18 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int n = nt * 16 + lg + 4 * r;
-        const double* wx = net + lay.Wx[k] + n * 3;
+        const double* ck = cst + (k - 1) * 6 * H + n;
+        const double wx[3] = {ck[3 * H], ck[4 * H], ck[5 * H]};
         const double da = acc[0][r] + wx[0] * x[0] + wx[1] * x[1] + wx[2] * x[2];
         double jk[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) jk[i] = acc[1 + i][r] + wx[i];
         double s_, sb_;
-        dz[r] = delta_softplus(da, net[lay.a0 + k * H + n], net[lay.s0 + k * H + n], net[lay.sb0 + k * H + n],
-                               s_, sb_);
+        dz[r] = delta_softplus(da, ck[0], ck[H], ck[2 * H], s_, sb_);
 #pragma unroll
         for (int i = 0; i < 3; ++i) zt[r][i] = s_ * jk[i];
         if (k == L - 1) {
-          const double wz = net[lay.wz + n];
+          const double wz = cst[(L - 1) * 6 * H + n];
           part[0] += wz * dz[r];
 #pragma unroll
           for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
