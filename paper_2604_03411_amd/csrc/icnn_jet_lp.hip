@@ -52,7 +52,12 @@ struct LpCfg {
   static constexpr int Z_BYTES = 4 * QB * HP * 2;
   static constexpr int X_BYTES = QB * 3 * 4;
   static constexpr int RED_BYTES = NT * QB * 10 * 4;
-  static constexpr int LDS_BYTES = (Z_BYTES > RED_BYTES ? Z_BYTES : RED_BYTES) + X_BYTES;
+  // per-neuron constants in FP32, staged once per block: for every layer k
+  // (a0, s0, sb0) at fields 3k..3k+2, then W0 (3), Wx of layers 1..L-1 (3
+  // each) and wz: 6L + 1 fields of H
+  static constexpr int NF = 6 * L + 1;
+  static constexpr int C_BYTES = NF * H * 4;
+  static constexpr int LDS_BYTES = (Z_BYTES > RED_BYTES ? Z_BYTES : RED_BYTES) + X_BYTES + C_BYTES;
   static_assert(WAVES % NT == 0, "waves must cover the neuron tiles");
 };
 
@@ -71,6 +76,7 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
   T* Zs = reinterpret_cast<T*>(lds_raw);
   float* red = reinterpret_cast<float*>(lds_raw);
   float* xs = reinterpret_cast<float*>(lds_raw + (C::Z_BYTES > C::RED_BYTES ? C::Z_BYTES : C::RED_BYTES));
+  float* cf = xs + QB * 3;  // [field][neuron]
   const NetLayout lay = make_layout_hd(3, H, L, 3);
   const double* __restrict__ net = a.net;
 
@@ -92,6 +98,22 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
         Wf[k - 1][s][t] = (m < H) ? from_bits<T>(Wk[(nt * 16 + li) * WHP + m]) : from_bits<T>(0);
         Wb[k - 1][s][t] = (m < H) ? from_bits<T>(Wk[m * WHP + nt * 16 + li]) : from_bits<T>(0);
       }
+  for (int idx = threadIdx.x; idx < C::NF * H; idx += blockDim.x) {
+    const int f = idx / H, n = idx % H;
+    double v;
+    if (f < 3 * L) {
+      const int k = f / 3, g = f % 3;
+      v = net[(g == 0 ? lay.a0 : g == 1 ? lay.s0 : lay.sb0) + k * H + n];
+    } else if (f < 3 * L + 3) {
+      v = net[lay.W0 + n * 3 + (f - 3 * L)];
+    } else if (f < 6 * L) {
+      const int k = 1 + (f - 3 * L - 3) / 3, i = (f - 3 * L - 3) % 3;
+      v = net[lay.Wx[k] + n * 3 + i];
+    } else {
+      v = net[lay.wz + n];
+    }
+    cf[idx] = (float)v;
+  }
   // zero the K padding of the activation rows once (never written afterwards)
   if (C::KP > H)
     for (int idx = threadIdx.x; idx < 4 * QB * HP; idx += blockDim.x)
@@ -117,16 +139,14 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int n = nt * 16 + 4 * lg + r;
-      const float w0 = (float)net[lay.W0 + n * 3], w1 = (float)net[lay.W0 + n * 3 + 1],
-                  w2 = (float)net[lay.W0 + n * 3 + 2];
+      const float w0 = cf[(3 * L) * H + n], w1 = cf[(3 * L + 1) * H + n], w2 = cf[(3 * L + 2) * H + n];
       const float da = w0 * x[0] + w1 * x[1] + w2 * x[2];
-      dz[r] = delta_softplus(da, (float)net[lay.a0 + n], (float)net[lay.s0 + n],
-                                    (float)net[lay.sb0 + n], sS[0][r], sB[0][r]);
+      dz[r] = delta_softplus(da, cf[n], cf[H + n], cf[2 * H + n], sS[0][r], sB[0][r]);
       Jt[0][r][0] = w0; Jt[0][r][1] = w1; Jt[0][r][2] = w2;
 #pragma unroll
       for (int i = 0; i < 3; ++i) zt[r][i] = sS[0][r] * Jt[0][r][i];
       if (L == 1) {
-        const float wz = (float)net[lay.wz + n];
+        const float wz = cf[6 * L * H + n];
         part[0] += wz * dz[r];
 #pragma unroll
         for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
@@ -175,17 +195,16 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int n = nt * 16 + 4 * lg + r;
-        const double* wx = net + lay.Wx[k] + n * 3;
-        const float wx0 = (float)wx[0], wx1 = (float)wx[1], wx2 = (float)wx[2];
+        const float* wx = cf + (3 * L + 3 + 3 * (k - 1)) * H + n;
+        const float wx0 = wx[0], wx1 = wx[H], wx2 = wx[2 * H];
         const float da = acc[0][r] + wx0 * x[0] + wx1 * x[1] + wx2 * x[2];
         const float jk[3] = {acc[1][r] + wx0, acc[2][r] + wx1, acc[3][r] + wx2};
         float s_, sb_;
-        dz[r] = delta_softplus(da, (float)net[lay.a0 + k * H + n], (float)net[lay.s0 + k * H + n],
-                                      (float)net[lay.sb0 + k * H + n], s_, sb_);
+        dz[r] = delta_softplus(da, cf[3 * k * H + n], cf[(3 * k + 1) * H + n], cf[(3 * k + 2) * H + n], s_, sb_);
 #pragma unroll
         for (int i = 0; i < 3; ++i) zt[r][i] = s_ * jk[i];
         if (k == L - 1) {
-          const float wz = (float)net[lay.wz + n];
+          const float wz = cf[6 * L * H + n];
           part[0] += wz * dz[r];
 #pragma unroll
           for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
