@@ -35,15 +35,17 @@ struct JetCfg {
   static constexpr int QP = QB;            // activation row (doubles)
   static constexpr int Z_DBL = 4 * H * QP;
   static constexpr int X_DBL = QB * 3;
-  // backward-pass state of the middle layers 1 .. L-2 (logistic pair and the
-  // three input-Jacobian entries of each of a lane's 4 rows), lane-contiguous
-  static constexpr int ST_DBL = (L > 2 ? L - 2 : 0) * WAVES * 5 * 4 * 64;
-  // per-neuron constants of the hidden->hidden layers 1 .. L-1 (a0, s0, sb0 and
-  // the three input weights Wx), then the output weights wz; staged once per
-  // block so the activation phases read them from LDS instead of memory
-  static constexpr int C_DBL = (L - 1) * 6 * H + H;
+  // backward-pass state of the middle layer (L = 3): the logistic pair of each
+  // of a lane's 4 rows, lane-contiguous.  Its input Jacobian is recovered from
+  // the tangent activations zeta = s J that are still in the activation buffer.
+  static constexpr int ST_DBL = (L > 2 ? L - 2 : 0) * WAVES * 2 * 4 * 64;
+  // per-neuron constants of every hidden layer k (a0, s0, sb0 and the three
+  // input weights: W0 for k = 0, Wx for k >= 1), then the output weights wz;
+  // staged once per block so the tiles read them from LDS instead of memory
+  static constexpr int C_DBL = L * 6 * H + H;
   static constexpr int LDS_BYTES = 8 * (Z_DBL + X_DBL + ST_DBL + C_DBL);
   static_assert(NT * QB * 10 <= Z_DBL, "reduction buffer aliases the activation buffer");
+  static_assert(L <= 3, "the middle-layer Jacobian is recovered from the last activation buffer");
 };
 
 template <int H, int L>
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
   double* Zs = lds;
   double* xs = Zs + C::Z_DBL;
   double* st = xs + C::X_DBL;  // [layer-1][wave][field][row][lane]
-  double* cst = st + C::ST_DBL;  // [layer-1][a0, s0, sb0, wx0, wx1, wx2][neuron], then wz[neuron]
+  double* cst = st + C::ST_DBL;  // [layer][a0, s0, sb0, w0, w1, w2][neuron], then wz[neuron]
   double* red = Zs;  // reused after the backward pass
   const NetLayout lay = make_layout_hd(3, H, L, 3);
   const double* __restrict__ net = a.net;
@@ -66,22 +68,30 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
   const int nbatch = (a.nq + QB - 1) / QB;
   for (int idx = threadIdx.x; idx < C::C_DBL; idx += blockDim.x) {
     double v;
-    if (idx < (L - 1) * 6 * H) {
-      const int k = 1 + idx / (6 * H), f = (idx / H) % 6, n = idx % H;
+    if (idx < L * 6 * H) {
+      const int k = idx / (6 * H), f = (idx / H) % 6, n = idx % H;
       v = f == 0 ? net[lay.a0 + k * H + n]
         : f == 1 ? net[lay.s0 + k * H + n]
         : f == 2 ? net[lay.sb0 + k * H + n]
-                 : net[lay.Wx[k] + n * 3 + (f - 3)];
+        : net[(k == 0 ? lay.W0 : k == 1 ? lay.Wx[1] : lay.Wx[2]) + n * 3 + (f - 3)];
     } else {
-      v = net[lay.wz + idx - (L - 1) * 6 * H];
+      v = net[lay.wz + idx - L * 6 * H];
     }
     cst[idx] = v;
   }
+  static_assert(QB * 3 <= C::WAVES * 64, "one input value per thread");
+  // The next tile's inputs travel in a register of the first QB * 3 threads:
+  // requested at the start of a tile, stored to LDS at the start of the next.
+  const int xi = threadIdx.x;
+  double xnext = 0.0;
+  if (xi < QB * 3 && (long)blockIdx.x * QB + xi / 3 < a.nq) xnext = a.x[(long)blockIdx.x * QB * 3 + xi];
 
   for (int batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
     const long q0 = (long)batch * QB;
-    for (int idx = threadIdx.x; idx < QB * 3; idx += blockDim.x)
-      xs[idx] = (q0 + idx / 3 < a.nq) ? a.x[q0 * 3 + idx] : 0.0;
+    if (xi < QB * 3) xs[xi] = xnext;
+    const long q1 = (long)(batch + gridDim.x) * QB;
+    xnext = 0.0;
+    if (xi < QB * 3 && q1 + xi / 3 < a.nq) xnext = a.x[q1 * 3 + xi];
     __syncthreads();
     const double x[3] = {xs[j * 3], xs[j * 3 + 1], xs[j * 3 + 2]};
 
@@ -101,14 +111,15 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int n = nt * 16 + lg + 4 * r;
-      const double w0 = net[lay.W0 + n * 3], w1 = net[lay.W0 + n * 3 + 1], w2 = net[lay.W0 + n * 3 + 2];
+      const double* c0 = cst + n;
+      const double w0 = c0[3 * H], w1 = c0[4 * H], w2 = c0[5 * H];
       const double da = w0 * x[0] + w1 * x[1] + w2 * x[2];
-      dz[r] = delta_softplus(da, net[lay.a0 + n], net[lay.s0 + n], net[lay.sb0 + n], s0r[r], sb0r[r]);
+      dz[r] = delta_softplus(da, c0[0], c0[H], c0[2 * H], s0r[r], sb0r[r]);
       zt[r][0] = s0r[r] * w0;
       zt[r][1] = s0r[r] * w1;
       zt[r][2] = s0r[r] * w2;
       if (L == 1) {
-        const double wz = net[lay.wz + n];
+        const double wz = cst[L * 6 * H + n];
         part[0] += wz * dz[r];
 #pragma unroll
         for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
@@ -148,11 +159,11 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
           acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Zs[c * H * QP + zb], acc[c], 0, 0, 0);
       }
       __syncthreads();
-      double* stk = st + ((size_t)(k - 1) * NT + nt) * 5 * 4 * 64 + lane;
+      double* stk = st + ((size_t)(k - 1) * NT + nt) * 2 * 4 * 64 + lane;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int n = nt * 16 + lg + 4 * r;
-        const double* ck = cst + (k - 1) * 6 * H + n;
+        const double* ck = cst + k * 6 * H + n;
         const double wx[3] = {ck[3 * H], ck[4 * H], ck[5 * H]};
         const double da = acc[0][r] + wx[0] * x[0] + wx[1] * x[1] + wx[2] * x[2];
         double jk[3];
@@ -163,7 +174,7 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) zt[r][i] = s_ * jk[i];
         if (k == L - 1) {
-          const double wz = cst[(L - 1) * 6 * H + n];
+          const double wz = cst[L * 6 * H + n];
           part[0] += wz * dz[r];
 #pragma unroll
           for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
@@ -180,8 +191,6 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
         } else if (hess) {
           stk[(0 * 4 + r) * 64] = s_;
           stk[(1 * 4 + r) * 64] = sb_;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) stk[((2 + i) * 4 + r) * 64] = jk[i];
         }
       }
     }
@@ -199,22 +208,26 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
         for (int s = 0; s < NS; ++s)
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wt[s * 64], Zs[(4 * s + lg) * QP + li], acc, 0, 0, 0);
         __syncthreads();
-        const double* stk = st + ((size_t)(k - 2) * NT + nt) * 5 * 4 * 64 + lane;
+        const double* stk = st + ((size_t)(k - 2) * NT + nt) * 2 * 4 * 64 + lane;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           double sv, sbv, Jr[3];
+          const int n = nt * 16 + lg + 4 * r;
           if (k - 1 == 0) {
-            const int n = nt * 16 + lg + 4 * r;
             sv = s0r[r];
             sbv = sb0r[r];
-            Jr[0] = net[lay.W0 + n * 3];
-            Jr[1] = net[lay.W0 + n * 3 + 1];
-            Jr[2] = net[lay.W0 + n * 3 + 2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Jr[i] = cst[(3 + i) * H + n];
           } else {
+            // J = zeta / s from the tangent activations of this layer, which
+            // are still in columns 1..3 of the activation buffer (the backward
+            // products only overwrite column 0); where s underflows the Hessian
+            // term s (1 - s) J J vanishes and J is taken as 0
             sv = stk[(0 * 4 + r) * 64];
             sbv = stk[(1 * 4 + r) * 64];
+            const double rs = (sv > 1e-290) ? rcp_d(sv) : 0.0;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) Jr[i] = stk[((2 + i) * 4 + r) * 64];
+            for (int i = 0; i < 3; ++i) Jr[i] = Zs[(1 + i) * H * QP + n * QP + j] * rs;
           }
           abar[r] = acc[r] * sv;
           const double c2 = abar[r] * sbv;
