@@ -172,6 +172,84 @@ __device__ __forceinline__ double delta_softplus(double d, double a0, double s0,
   return (fa ? 0.0 : d) + log1p_pair(p * M, w);
 }
 
+// ---- table-driven variants; the caller stages the kMathTabDoubles-entry table
+// (exp: 64 x (Thi, Tlo); log: 64 x (1/c, log c hi, log c lo, 0); built on the
+// host by build_math_tables) in LDS.
+// exp / expm1: t = (64 n + j) ln2/64 + r with |r| <= ln2/128 (ln2/64 split so
+// that the products with the integer multiple are exact), 2^(j/64) = Thi + Tlo
+// from the table, expm1(r) by its Taylor series through r^6 (truncation below
+// 1e-17 relative).  E = e^t = 2^n (Thi + tmp) and M = e^t - 1 =
+// 2^n ((Thi - 2^-n) + tmp) with tmp = Thi expm1(r) + Tlo; Thi - 2^-n is exact
+// (or dominated by the power of two), so M keeps relative precision at t -> 0.
+// log1p: w = 2^e z with z in [0.6875, 1.375) by integer arithmetic on the high
+// word; 64 intervals of z with 1/c_i from the table (exactly 1 on the two
+// intervals next to 1), r = z / c_i - 1 by one fused rounding, |r| <= 1/64,
+// log1p(r) by its series through r^9; log w = e ln2 + log c_i + log1p(r).  For
+// y > -1/2 the argument is w = 1 + y with the exact rounding error of that sum
+// added as err / w, so small |y| keep relative precision; otherwise an
+// accurate w from the caller.  Table indices are masked to 0..63 whatever the
+// input; NaN inputs propagate.
+constexpr double kTabC1 = 0x1.62e42fefa0000p-7, kTabC2 = 0x1.cf79abc9e3b3ap-46;  // ln2/64
+constexpr double kTabInv = 0x1.71547652b82fep+6;                                 // 64/ln2
+constexpr double kLn2Hi32 = 0x1.62e42fee00000p-1, kLn2Lo32 = 0x1.a39ef35793c76p-33;
+
+__device__ __forceinline__ void exp_expm1_tab(double t, const double* __restrict__ et, double& E, double& M) {
+  t = (t < -700.0) ? -700.0 : ((t > 700.0) ? 700.0 : t);
+  const double kk = rint(t * kTabInv);
+  const int ki = (int)kk;
+  const double r = fma(-kk, kTabC2, fma(-kk, kTabC1, t));
+  const int j = ki & 63, n = ki >> 6;
+  double q = fma(r, 1.0 / 720.0, 1.0 / 120.0);
+  q = fma(q, r, 1.0 / 24.0);
+  q = fma(q, r, 1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  const double em = fma(r * r, q, r);
+  const double thi = et[2 * j], tlo = et[2 * j + 1];
+  const double tmp = fma(thi, em, tlo);
+  E = ldexp(thi + tmp, n);
+  M = ldexp((thi - ldexp(1.0, -n)) + tmp, n);
+}
+
+__device__ __forceinline__ double log1p_tab(double y, double wacc, double winv, const double* __restrict__ lt) {
+  const bool small = y > -0.5;
+  const double ws = 1.0 + y;
+  const double w = small ? ws : wacc;
+  const double err = small ? y - (ws - 1.0) : 0.0;
+  const int hi = __double2hiint(w);
+  const int tmp = hi - 0x3FE60000;
+  const int e = tmp >> 20;
+  const int i = (tmp >> 14) & 63;
+  const double z = __hiloint2double(hi - (e << 20), __double2loint(w));
+  const double invc = lt[4 * i], lhi = lt[4 * i + 1], llo = lt[4 * i + 2];
+  const double r = fma(z, invc, -1.0);
+  double q = fma(r, 1.0 / 9.0, -1.0 / 8.0);
+  q = fma(q, r, 1.0 / 7.0);
+  q = fma(q, r, -1.0 / 6.0);
+  q = fma(q, r, 1.0 / 5.0);
+  q = fma(q, r, -0.25);
+  q = fma(q, r, 1.0 / 3.0);
+  q = fma(q, r, -0.5);
+  const double ed = (double)e;
+  const double res = fma(ed, kLn2Hi32, lhi) + (fma(r * r, q, r) + fma(err, winv, fma(ed, kLn2Lo32, llo)));
+  return fma(0.0, y, res);  // keeps a NaN y
+}
+
+// delta_softplus with the table-driven exp / log1p.
+__device__ __forceinline__ double delta_softplus_tab(double d, double a0, double s0, double sb0, double& s,
+                                                     double& sb, const double* __restrict__ et,
+                                                     const double* __restrict__ lt) {
+  const bool fa = a0 + d <= 0.0;
+  double E, M;
+  exp_expm1_tab(fa ? d : -d, et, E, M);
+  const double p = fa ? s0 : sb0, c = fa ? sb0 : s0;
+  const double w = fma(p, E, c);
+  const double inv = rcp_d(w);
+  const double sp = p * E * inv, sc = c * inv;
+  s = fa ? sp : sc;
+  sb = fa ? sc : sp;
+  return (fa ? 0.0 : d) + log1p_tab(p * M, w, inv, lt);
+}
+
 // FP32 version for the mixed-precision jets (same forms, hardware exp / log /
 // reciprocal; expm1 and log1p of small arguments by their Taylor / atanh
 // series, so small increments keep relative precision).

@@ -683,7 +683,31 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   __syncthreads();
 
   // ---------------- element residual: lanes own element dofs
-  {
+  // (Hex8: the two halves of the wavefront integrate points 0..3 and 4..7 of
+  // the same 32 dofs and are summed with one lane exchange)
+  if constexpr (DIM == 3) {
+    const int dl = lane & 31, hq = lane >> 5;
+    const int an = dl / T::ND, cc = dl % T::ND;
+    double acc = 0.0;
+#pragma unroll 1
+    for (int qq = 0; qq < 4; ++qq) {
+      const int gq = hq * 4 + qq;
+      double t;
+      if (cc < DIM) {
+        t = 0.0;
+#pragma unroll
+        for (int J = 0; J < DIM; ++J) t += S.G[gq][an][J] * S.Pz[gq][cc * DIM + J];
+      } else {
+        const int zp = DIM * DIM;
+        t = S.N[gq][an] * S.Pz[gq][zp];
+#pragma unroll
+        for (int J = 0; J < DIM; ++J) t += S.G[gq][an][J] * S.Pz[gq][zp + 1 + J];
+      }
+      acc += S.Jw[gq] * t;
+    }
+    acc += __shfl_xor(acc, 32, 64);
+    if (r_own) a.R[r_idx] = r_old + acc;
+  } else {
     const int eslot = r_slot;
     const int dl = r_dl;
     if (r_own) {

@@ -77,6 +77,7 @@ struct JetArgs {
   int nq;
   int L;
   int with_hessian;
+  const double* mtab;    // [kMathTabDoubles] exp / log tables (FP64 kernel)
 };
 
 struct KinArgs {
@@ -129,6 +130,10 @@ struct ElemArgs {
   double n0;                 // energy network dN/dx3 at 0
 };
 
+// Host: the exp / log tables of the table-driven FP64 functions.
+constexpr int kMathTabDoubles = 64 * 2 + 64 * 4;
+void build_math_tables(std::vector<double>& t);
+
 // Kernel launchers (defined in the .hip translation units).
 hipError_t launch_qp_inputs(int dim, const KinArgs& a, hipStream_t s);
 hipError_t launch_energy_jet(int precision, int H, const JetArgs& a, hipStream_t s, int num_cu);
@@ -174,6 +179,7 @@ struct gedmg_ctx {
   uint16_t* dw_bf16 = nullptr;         // low-precision hidden weights
   uint16_t* dw_f16 = nullptr;
   double* dwop = nullptr;              // FP64 hidden weights in operand order (JetArgs::wop)
+  double* dmtab = nullptr;             // exp / log tables of the FP64 jets (JetArgs::mtab)
   double* dx = nullptr;                // [nq][3]
   double* djet = nullptr;              // [nq][10]
   double* dphiq = nullptr;             // [nq]

@@ -43,7 +43,8 @@ struct JetCfg {
   // input weights: W0 for k = 0, Wx for k >= 1), then the output weights wz;
   // staged once per block so the tiles read them from LDS instead of memory
   static constexpr int C_DBL = L * 6 * H + H;
-  static constexpr int LDS_BYTES = 8 * (Z_DBL + X_DBL + ST_DBL + C_DBL);
+  static constexpr int M_DBL = kMathTabDoubles;  // exp / log tables
+  static constexpr int LDS_BYTES = 8 * (Z_DBL + X_DBL + ST_DBL + C_DBL + M_DBL);
   static_assert(NT * QB * 10 <= Z_DBL, "reduction buffer aliases the activation buffer");
   static_assert(L <= 3, "the middle-layer Jacobian is recovered from the last activation buffer");
 };
@@ -57,6 +58,9 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
   double* xs = Zs + C::Z_DBL;
   double* st = xs + C::X_DBL;  // [layer-1][wave][field][row][lane]
   double* cst = st + C::ST_DBL;  // [layer][a0, s0, sb0, w0, w1, w2][neuron], then wz[neuron]
+  double* mt = cst + C::C_DBL;   // exp table [64][2], then log table [64][4]
+  const double* et = mt;
+  const double* lt = mt + 128;
   double* red = Zs;  // reused after the backward pass
   const NetLayout lay = make_layout_hd(3, H, L, 3);
   const double* __restrict__ net = a.net;
@@ -79,6 +83,7 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
     }
     cst[idx] = v;
   }
+  for (int idx = threadIdx.x; idx < C::M_DBL; idx += blockDim.x) mt[idx] = a.mtab[idx];
   static_assert(QB * 3 <= C::WAVES * 64, "one input value per thread");
   // The next tile's inputs travel in a register of the first QB * 3 threads:
   // requested at the start of a tile, stored to LDS at the start of the next.
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
       const double* c0 = cst + n;
       const double w0 = c0[3 * H], w1 = c0[4 * H], w2 = c0[5 * H];
       const double da = w0 * x[0] + w1 * x[1] + w2 * x[2];
-      dz[r] = delta_softplus(da, c0[0], c0[H], c0[2 * H], s0r[r], sb0r[r]);
+      dz[r] = delta_softplus_tab(da, c0[0], c0[H], c0[2 * H], s0r[r], sb0r[r], et, lt);
       zt[r][0] = s0r[r] * w0;
       zt[r][1] = s0r[r] * w1;
       zt[r][2] = s0r[r] * w2;
@@ -170,7 +175,7 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) jk[i] = acc[1 + i][r] + wx[i];
         double s_, sb_;
-        dz[r] = delta_softplus(da, ck[0], ck[H], ck[2 * H], s_, sb_);
+        dz[r] = delta_softplus_tab(da, ck[0], ck[H], ck[2 * H], s_, sb_, et, lt);
 #pragma unroll
         for (int i = 0; i < 3; ++i) zt[r][i] = s_ * jk[i];
         if (k == L - 1) {

@@ -87,6 +87,39 @@ hipError_t launch_energy_jet(int precision, int H, const JetArgs& a, hipStream_t
   return launch_energy_jet_lp(precision, H, a, s, num_cu);
 }
 
+// Tables of the table-driven FP64 exp / log1p (device_common.h), in extended
+// precision: exp 2^(j/64) = hi + lo; log over the 64 intervals of
+// z in [0.6875, 1.375) that the high-word index selects: 1/c with c the
+// interval's centre (exactly 1 on the two intervals next to 1, so small
+// arguments keep relative precision) and -log(1/c) = hi + lo.
+void build_math_tables(std::vector<double>& t) {
+  t.assign(kMathTabDoubles, 0.0);
+  for (int j = 0; j < 64; ++j) {
+    const long double v = exp2l((long double)j / 64.0L);
+    const double hi = (double)v;
+    t[2 * j] = hi;
+    t[2 * j + 1] = (double)(v - (long double)hi);
+  }
+  auto from_hi = [](uint32_t hw) {
+    const uint64_t u = (uint64_t)hw << 32;
+    double d;
+    std::memcpy(&d, &u, 8);
+    return d;
+  };
+  for (int i = 0; i < 64; ++i) {
+    const double zlo = from_hi(0x3FE60000u + ((uint32_t)i << 14));
+    const double zhi = from_hi(0x3FE60000u + ((uint32_t)(i + 1) << 14));
+    const double invc = (i == 39 || i == 40) ? 1.0 : (double)(2.0L / ((long double)zlo + (long double)zhi));
+    const long double lc = -logl((long double)invc);
+    const double hi = (double)lc;
+    double* e = &t[128 + 4 * i];
+    e[0] = invc;
+    e[1] = hi;
+    e[2] = (double)(lc - (long double)hi);
+    e[3] = 0.0;
+  }
+}
+
 }  // namespace gedmg
 
 namespace {
@@ -162,7 +195,8 @@ int upload_params(gedmg_ctx* c, const double* te, const double* ty) {
 
 void free_all(gedmg_ctx* c) {
   void* ptrs[] = {c->dX, c->dconn, c->dperm, c->dblk, c->drowstride, c->dfirst, c->drowptr, c->dcol,
-                  c->denet, c->dynet, c->dw_bf16, c->dw_f16, c->dwop, c->dx, c->djet, c->dphiq, c->dsens, c->dstatus};
+                  c->denet, c->dynet, c->dw_bf16, c->dw_f16, c->dwop, c->dmtab, c->dx, c->djet, c->dphiq, c->dsens,
+                  c->dstatus};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -328,8 +362,14 @@ int gedmg_create(gedmg_ctx** out, const gedmg_mesh* mesh, const gedmg_material* 
   const size_t wlp = (size_t)std::max(c->elay.L - 1, 1) * c->elay.H * (c->elay.H + 8);
   if ((rc = dalloc(c, &c->denet, c->elay.total)) || (rc = dalloc(c, &c->dynet, c->ylay.total)) ||
       (rc = dalloc(c, &c->dw_bf16, wlp)) || (rc = dalloc(c, &c->dw_f16, wlp)) ||
-      (rc = dalloc(c, &c->dwop, (size_t)std::max(c->elay.L - 1, 1) * 2 * c->elay.H * c->elay.H)))
+      (rc = dalloc(c, &c->dwop, (size_t)std::max(c->elay.L - 1, 1) * 2 * c->elay.H * c->elay.H)) ||
+      (rc = dalloc(c, &c->dmtab, kMathTabDoubles)))
     return fail(rc);
+  {
+    std::vector<double> mt;
+    build_math_tables(mt);
+    GEDMG_HIP(c, hipMemcpy(c->dmtab, mt.data(), sizeof(double) * mt.size(), hipMemcpyHostToDevice));
+  }
   if ((rc = upload_params(c, energy->theta, yield->theta))) return fail(rc);
   *out = c;
   return GEDMG_OK;
@@ -388,7 +428,7 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[2], c->stream));
   const int64_t nq = (int64_t)c->n_elems * c->nqp;
   JetArgs ja{c->dx, c->djet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16, c->dwop,
-             (int)nq, c->elay.L, K_vals ? 1 : 0};
+             (int)nq, c->elay.L, K_vals ? 1 : 0, c->dmtab};
   GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[3], c->stream));
   HistArgs ha{c->dx, c->djet, c->dphiq, kappa_n, c->dynet, kappa_trial, c->dsens, c->dstatus, (long)nq,
@@ -450,7 +490,7 @@ int gedmg_energy_jet(gedmg_ctx* c, const double* x, int64_t n, int precision, do
     return GEDMG_E_ARG;
   }
   JetArgs ja{x, jet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16, c->dwop, (int)n,
-             c->elay.L, 1};
+             c->elay.L, 1, c->dmtab};
   GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
   return GEDMG_OK;
 }
