@@ -173,17 +173,15 @@ __global__ void reduce_kernel(const double* part, double* scal, int slot, int sl
   }
 }
 
-// ---- CG pieces
-__global__ void cg_alpha_kernel(double* scal) {
-  const double pap = scal[S_PAP];
-  if (!(pap > 0.0)) scal[S_FLAG] = 1.0;  // non-positive curvature
-  scal[S_ALPHA] = (pap > 0.0) ? scal[S_RZ] / pap : 0.0;
-}
-
+// ---- CG pieces.  r.z alternates between two slots (ra holds the current
+// value, rb receives the next), so every block forms alpha and beta itself and
+// no single-thread scalar kernel sits between the vector kernels.
 __global__ void cg_update_kernel(double* x, double* r, double* z, const double* p, const double* Ap,
-                                 const double* dinv, const double* scal, long n, double* part) {
+                                 const double* dinv, double* scal, int ra, long n, double* part) {
   __shared__ double sh[8];
-  const double alpha = scal[S_ALPHA];
+  const double pap = scal[S_PAP];
+  const double alpha = (pap > 0.0) ? scal[ra] / pap : 0.0;
+  if (!(pap > 0.0) && blockIdx.x == 0 && threadIdx.x == 0) scal[S_FLAG] = 1.0;  // non-positive curvature
   double s1 = 0.0, s2 = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     x[i] += alpha * p[i];
@@ -200,14 +198,10 @@ __global__ void cg_update_kernel(double* x, double* r, double* z, const double* 
   if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = t2;
 }
 
-__global__ void cg_beta_kernel(double* scal) {
-  const double rz = scal[S_RZ];
-  scal[S_BETA] = (rz != 0.0) ? scal[S_RZNEW] / rz : 0.0;
-  scal[S_RZ] = scal[S_RZNEW];
-}
-
-__global__ void cg_p_kernel(double* p, const double* z, const double* scal, long n) {
-  const double beta = scal[S_BETA];
+// p = z + beta p with beta = (r.z)_new / (r.z)
+__global__ void cg_p_kernel(double* p, const double* z, const double* scal, int ra, int rb, long n) {
+  const double rz = scal[ra];
+  const double beta = (rz != 0.0) ? scal[rb] / rz : 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     p[i] = z[i] + beta * p[i];
 }
@@ -429,13 +423,12 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
   const int check = 8;
   bool use_bicg = false;
   for (int it = 1; it <= max_it; ++it) {
+    const int ra = (it & 1) ? S_RZ : S_RZNEW, rb = (it & 1) ? S_RZNEW : S_RZ;
     if ((rc = spmv(c, w, K, w.p, w.q, w.p, S_PAP))) return rc;
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(1), 0, c->stream, w.scal);
     hipLaunchKernelGGL(cg_update_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.x, w.r, w.z, w.p, w.q,
-                       w.dinv, w.scal, n, w.part);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_RZNEW, S_RR);
-    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(1), 0, c->stream, w.scal);
-    hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.z, w.scal, n);
+                       w.dinv, w.scal, ra, n, w.part);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, rb, S_RR);
+    hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.z, w.scal, ra, rb, n);
     GH(hipGetLastError());
     *its = it;
     if (it % check == 0 || it == max_it) {
