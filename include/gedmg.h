@@ -151,7 +151,8 @@ int gedmg_csr(gedmg_ctx* ctx, int64_t* n_rows, int64_t* nnz, const int32_t** row
  * included), K_vals[nnz] = consistent tangent in the CSR pattern (NULL:
  * residual only, skips the tangent; otherwise 16-byte aligned, and every entry
  * is overwritten, so it needs no clearing), kappa_trial[n_elems][nqp] = history after
- * the local update.  precision selects the arithmetic of the energy-network
+ * the local update (it may be the kappa_n array itself: every point reads its
+ * kappa_n before writing).  precision selects the arithmetic of the energy-network
  * layer products: GEDMG_FP64, or GEDMG_BF16 / GEDMG_FP16 matrix-core products
  * with FP32 accumulation (everything else stays FP64).
  * GEDMG_E_LOCAL_NOCONV / GEDMG_E_JNONPOS are reported by a later synchronising
