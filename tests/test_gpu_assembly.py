@@ -65,3 +65,23 @@ def test_assembly_is_deterministic(G):
     sync()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_kappa_trial_may_alias_kappa_n(G, cfg):
+    """Passing the history array as both kappa_n and kappa_trial gives the same
+    R, K and updated history as separate arrays (each point reads its kappa_n
+    before the update writes it)."""
+    case = small_case(cfg)
+    u, phi, kap = state(case, 9 + cfg)
+    ctx = G.Context.from_case(case)
+    uu, pp, kk = ctx.fields(u, phi, kap)
+    R1, K1, k1 = [t.clone() for t in ctx.assemble(uu, pp, kk, "fp64")]
+    R2 = torch.empty_like(R1)
+    K2 = torch.empty_like(K1)
+    R2, K2, k2 = ctx.assemble(uu, pp, kk, "fp64", out=(R2, K2, kk))
+    sync()
+    assert k2.data_ptr() == kk.data_ptr()
+    for x, y in ((R1, R2), (K1, K2), (k1, k2)):
+        assert torch.equal(x, y)
+    ctx.close()
