@@ -163,7 +163,9 @@ int gedmg_assemble(gedmg_ctx* ctx, const double* u, const double* phi, const dou
 /* Diagnostic: the energy-network jet at given inputs, in the arithmetic
  * selected by precision (used by the tests and by the mixed-precision error
  * report).  x: device [n][3] inputs (I1G - 3, I2G - 3, J - 1); jet: device
- * [n][10] = N(x) - N(0), dN/dx (3), d2N/dx2 (xx, yy, zz, xy, xz, yz). */
+ * [n][10] = N(x) - N(0), dN/dx (3), d2N/dx2 (xx, yy, zz, xy, xz, yz).
+ * n = 0 is a no-op (x and jet may then be NULL); n above 2^31 - 1 is
+ * GEDMG_E_ARG. */
 int gedmg_energy_jet(gedmg_ctx* ctx, const double* x, int64_t n, int precision, double* jet);
 
 /* Per-phase timing of gedmg_assemble with HIP events recorded on the

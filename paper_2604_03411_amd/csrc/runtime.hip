@@ -484,7 +484,7 @@ int gedmg_profile_read(gedmg_ctx* c, double* out, int32_t* n_calls) {
 
 int gedmg_energy_jet(gedmg_ctx* c, const double* x, int64_t n, int precision, double* jet) {
   if (!c) return GEDMG_E_ARG;
-  if (!x || !jet || n < 0 || n > INT32_MAX) { c->err = "bad jet arguments"; return GEDMG_E_ARG; }
+  if (n < 0 || n > INT32_MAX || (n > 0 && (!x || !jet))) { c->err = "bad jet arguments"; return GEDMG_E_ARG; }
   if (precision != GEDMG_FP64 && precision != GEDMG_BF16 && precision != GEDMG_FP16) {
     c->err = "unknown precision";
     return GEDMG_E_ARG;
