@@ -444,10 +444,11 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
   // ---------------- gather and kinematics (lane sub serves node sub)
   const bool has_node = valid && sub < T::NEN;
   int node = 0;
-  if (has_node) node = a.conn[(long)e * T::NEN + sub];
+  if (has_node) node = a.conn_s[(long)pe * T::NEN + sub];
   // Loads that do not depend on the connectivity, issued before the gather
   // chain so that their latency overlaps it: this point's jet row, updated
-  // history and its sensitivities.
+  // history and its sensitivities, the node coordinates, and (Hex8 tangent)
+  // the CSR segments this lane writes at the end.
   d2_t jv[5] = {}, sens = {};
   double kap = 0.0;
   if (valid) {
@@ -457,11 +458,19 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     kap = a.kappa[qg];
     sens = reinterpret_cast<const d2_t*>(a.sens)[qg];
   }
+  constexpr int SPL = (DIM == 3 && TANGENT) ? T::NDOFE * T::NEN / 64 : 1;  // segments per lane
+  uint32_t segv[SPL];
+#pragma unroll
+  for (int t = 0; t < SPL; ++t) segv[t] = 0u;
+  if (DIM == 3 && TANGENT && valid) {
+#pragma unroll
+    for (int t = 0; t < SPL; ++t) segv[t] = (uint32_t)a.seg[(long)slot_base * (T::NDOFE * T::NEN) + lane + 64 * t];
+  }
   double Xn[DIM] = {}, un[DIM] = {}, phin = 0.0, Nv = 0.0, dN[DIM] = {};
   if (has_node) {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      Xn[d] = a.X[(long)d * a.n_nodes + node];
+      Xn[d] = a.Xs[((long)pe * DIM + d) * T::NEN + sub];
       un[d] = a.u[(long)d * a.n_nodes + node];
     }
     phin = a.phi[node];
@@ -745,38 +754,17 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
     //   K[(an, 2h + 1)] += N_an T[3] + G_an . T[4..6]
     const int h = lane >> 5, col = lane & 31;
     const int bnode = col >> 2, kc = col & 3;
-    const int ae = a.perm[slot_base];
-    // the segments this lane writes afterwards: issue their old values now,
-    // so the loads complete while the tangent is integrated
-    // (index loads of all segments first, then the value loads: loads complete
-    // in order, so an index wait placed after a value load would wait for it)
-    constexpr int SPL = T::NDOFE * T::NEN / 64;  // segments per lane
+    // the segments this lane writes afterwards (offsets loaded in the
+    // prologue): issue their old values now, so the loads complete while the
+    // tangent is integrated
     long soff[SPL];
     bool sfirst[SPL];
     d2_t old0[SPL], old1[SPL];
-    int nodea_t[SPL], blk_t[SPL];
-    const uint64_t fbits = a.first[ae];
 #pragma unroll
     for (int t = 0; t < SPL; ++t) {
-      const int sg = lane + 64 * t;
-      const int r = sg / T::NEN, bn = sg % T::NEN;
-      const int an = r / T::ND;
-      nodea_t[t] = a.conn[(long)ae * T::NEN + an];
-      blk_t[t] = a.blk[((long)ae * T::NEN + an) * T::NEN + bn];
+      soff[t] = (long)(segv[t] & 0x7fffffffu);
+      sfirst[t] = (segv[t] >> 31) != 0u;
     }
-#pragma unroll
-    for (int t = 0; t < SPL; ++t) {
-      const int sg = lane + 64 * t;
-      const int r = sg / T::NEN, bn = sg % T::NEN;
-      const int an = r / T::ND, cr = r % T::ND;
-      soff[t] = (long)blk_t[t] + (long)cr * a.rowstride[nodea_t[t]];
-      sfirst[t] = (fbits >> (an * T::NEN + bn)) & 1ull;
-    }
-    // Materialise every offset before the first value load (an empty asm that
-    // takes the offsets as operands), so no value load waits on index loads.
-#pragma unroll
-    for (int t = 0; t < SPL; ++t) asm volatile("" : "+v"(soff[t]));
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int t = 0; t < SPL; ++t) {
       old0[t] = d2_t{0.0, 0.0};
@@ -912,12 +900,10 @@ __global__ __launch_bounds__(64) void element_kernel(ElemArgs a) {
       const int rem = sg - es * (T::NDOFE * T::NEN);
       const int r = rem / T::NEN, bn = rem % T::NEN;
       if (slot_base + es >= a.e_end) continue;
-      const int ae = a.perm[slot_base + es];
-      const int an = r / T::ND, cr = r % T::ND;
-      const int nodea = a.conn[(long)ae * T::NEN + an];
-      const long off = (long)a.blk[((long)ae * T::NEN + an) * T::NEN + bn] + (long)cr * a.rowstride[nodea];
+      const uint32_t sv = (uint32_t)a.seg[(long)(slot_base + es) * (T::NDOFE * T::NEN) + rem];
+      const long off = (long)(sv & 0x7fffffffu);
       const double* src = &S.D[0][0][0] + es * T::NDOFE * T::NDOFE + r * T::NDOFE + bn * T::ND;
-      const bool first = (a.first[ae] >> (an * T::NEN + bn)) & 1ull;
+      const bool first = (sv >> 31) != 0u;
       double v[T::ND];
 #pragma unroll
       for (int k = 0; k < T::ND; ++k) v[k] = src[k];

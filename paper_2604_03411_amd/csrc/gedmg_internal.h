@@ -109,13 +109,16 @@ struct HistArgs {
   int max_local;
 };
 
+// Mesh data of the element kernel are stored by colour slot (the position of
+// the element in perm), so a wavefront reaches its element's nodes and CSR
+// segments without first loading the element number.
 struct ElemArgs {
-  const double* X;
-  const int32_t* conn;
-  const int32_t* perm;       // elements sorted by colour
-  const int32_t* blk;        // [n_elems][nen][nen] CSR offset of block (a,b) row 0
-  const int32_t* rowstride;  // [n_nodes] CSR row length of the node's rows
-  const uint64_t* first;     // [n_elems] bit a*nen+b: this element is the first (lowest colour) to write block (a,b)
+  const double* Xs;          // [n_elems][dim][nen] node coordinates, by slot
+  const int32_t* conn_s;     // [n_elems][nen] connectivity, by slot
+  const int32_t* perm;       // slot -> element (elements sorted by colour)
+  const int32_t* seg;        // [n_elems][nen * nd][nen], by slot: CSR offset of the nd values of element row
+                             // (a, c) in node block (a, b); bit 31 set: this element is the first (lowest
+                             // colour) to write block (a, b)
   const double* u;
   const double* phi;
   const double* jet;         // [n_elems*nqp][10]
@@ -169,9 +172,9 @@ struct gedmg_ctx {
   double* dX = nullptr;
   int32_t* dconn = nullptr;
   int32_t* dperm = nullptr;
-  int32_t* dblk = nullptr;
-  int32_t* drowstride = nullptr;
-  uint64_t* dfirst = nullptr;          // first-writer bits per element (see ElemArgs)
+  double* dXs = nullptr;               // element-kernel mesh data by colour slot (see ElemArgs)
+  int32_t* dconn_s = nullptr;
+  int32_t* dseg = nullptr;
   int32_t* drowptr = nullptr;
   int32_t* dcol = nullptr;
   double* denet = nullptr;             // packed energy network

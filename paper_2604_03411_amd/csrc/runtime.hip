@@ -194,7 +194,7 @@ int upload_params(gedmg_ctx* c, const double* te, const double* ty) {
 }
 
 void free_all(gedmg_ctx* c) {
-  void* ptrs[] = {c->dX, c->dconn, c->dperm, c->dblk, c->drowstride, c->dfirst, c->drowptr, c->dcol,
+  void* ptrs[] = {c->dX, c->dconn, c->dperm, c->dXs, c->dconn_s, c->dseg, c->drowptr, c->dcol,
                   c->denet, c->dynet, c->dw_bf16, c->dw_f16, c->dwop, c->dmtab, c->dx, c->djet, c->dphiq, c->dsens,
                   c->dstatus};
   for (void* p : ptrs)
@@ -334,11 +334,33 @@ int gedmg_create(gedmg_ctx** out, const gedmg_mesh* mesh, const gedmg_material* 
     for (int e = 0; e < ne; ++e) perm[fill[color[e]]++] = e;
   }
 
+  // ---- element-kernel mesh data by colour slot: node coordinates,
+  // connectivity, and the CSR offset of every nd-long segment (element row
+  // (a, c), node block column b) with the first-writer flag in bit 31 (the
+  // offsets are below 2^31 by the check on nnz)
+  const int nseg = nen * nd * nen;
+  std::vector<double> Xs((size_t)ne * c->dim * nen);
+  std::vector<int32_t> conn_s((size_t)ne * nen), seg((size_t)ne * nseg);
+  for (int sl = 0; sl < ne; ++sl) {
+    const int e = perm[sl];
+    for (int a = 0; a < nen; ++a) {
+      const int na = conn[(long)e * nen + a];
+      conn_s[(size_t)sl * nen + a] = na;
+      for (int d = 0; d < c->dim; ++d) Xs[((size_t)sl * c->dim + d) * nen + a] = mesh->X[(size_t)d * nn + na];
+      for (int cr = 0; cr < nd; ++cr)
+        for (int b = 0; b < nen; ++b) {
+          const uint32_t off = (uint32_t)blk[((size_t)e * nen + a) * nen + b] + (uint32_t)cr * (uint32_t)rowstride[na];
+          const uint32_t fw = (uint32_t)((first[e] >> (a * nen + b)) & 1ull);
+          seg[(size_t)sl * nseg + (size_t)(a * nd + cr) * nen + b] = (int32_t)(off | (fw << 31));
+        }
+    }
+  }
+
   // ---- device copies
   const int64_t nq = (int64_t)ne * c->nqp;
   if ((rc = dalloc(c, &c->dX, (size_t)c->dim * nn)) || (rc = dalloc(c, &c->dconn, (size_t)ne * nen)) ||
-      (rc = dalloc(c, &c->dperm, ne)) || (rc = dalloc(c, &c->dblk, blk.size())) ||
-      (rc = dalloc(c, &c->drowstride, nn)) || (rc = dalloc(c, &c->dfirst, (size_t)ne)) ||
+      (rc = dalloc(c, &c->dperm, ne)) || (rc = dalloc(c, &c->dXs, Xs.size())) ||
+      (rc = dalloc(c, &c->dconn_s, conn_s.size())) || (rc = dalloc(c, &c->dseg, seg.size())) ||
       (rc = dalloc(c, &c->drowptr, rowptr.size())) ||
       (rc = dalloc(c, &c->dcol, nnz)) || (rc = dalloc(c, &c->dx, (size_t)nq * 3)) ||
       (rc = dalloc(c, &c->djet, (size_t)nq * 10)) || (rc = dalloc(c, &c->dphiq, (size_t)nq)) ||
@@ -347,9 +369,9 @@ int gedmg_create(gedmg_ctx** out, const gedmg_mesh* mesh, const gedmg_material* 
   GEDMG_HIP(c, hipMemcpy(c->dX, mesh->X, sizeof(double) * c->dim * nn, hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemcpy(c->dconn, conn, sizeof(int32_t) * ne * nen, hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemcpy(c->dperm, perm.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice));
-  GEDMG_HIP(c, hipMemcpy(c->dblk, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice));
-  GEDMG_HIP(c, hipMemcpy(c->drowstride, rowstride.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice));
-  GEDMG_HIP(c, hipMemcpy(c->dfirst, first.data(), sizeof(uint64_t) * ne, hipMemcpyHostToDevice));
+  GEDMG_HIP(c, hipMemcpy(c->dXs, Xs.data(), sizeof(double) * Xs.size(), hipMemcpyHostToDevice));
+  GEDMG_HIP(c, hipMemcpy(c->dconn_s, conn_s.data(), sizeof(int32_t) * conn_s.size(), hipMemcpyHostToDevice));
+  GEDMG_HIP(c, hipMemcpy(c->dseg, seg.data(), sizeof(int32_t) * seg.size(), hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemcpy(c->drowptr, rowptr.data(), sizeof(int32_t) * rowptr.size(), hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemcpy(c->dcol, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemset(c->dstatus, 0, 4 * sizeof(int)));
@@ -436,8 +458,7 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
   GEDMG_HIP(c, launch_history(ha, c->ylay.H, c->stream));
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[4], c->stream));
   ElemArgs ea{};
-  ea.X = c->dX; ea.conn = c->dconn; ea.perm = c->dperm; ea.blk = c->dblk; ea.rowstride = c->drowstride;
-  ea.first = c->dfirst;
+  ea.Xs = c->dXs; ea.conn_s = c->dconn_s; ea.perm = c->dperm; ea.seg = c->dseg;
   ea.u = u; ea.phi = phi; ea.jet = c->djet; ea.kappa = kappa_trial; ea.sens = c->dsens;
   ea.R = R; ea.K = K_vals; ea.status = c->dstatus;
   ea.n_nodes = c->n_nodes; ea.n_elems = c->n_elems;
