@@ -24,21 +24,64 @@ __device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net
                                                   double& dN) {
   const int stride = H * H + 2 * H;  // Wz, Wx, b of one hidden layer
   const int owz = 2 * H + (L - 1) * stride;
-  double z[H], zt[H];
+  double pN = 0.0, pD = 0.0;
+  if constexpr (L == 1) {
+    // a single hidden layer: all of its weights fit in registers, and the
+    // unrolled form lets the neurons' instruction streams interleave
+    double z[H], zt[H];
 #pragma unroll
-  for (int n = 0; n < H; ++n) {
-    const double w = net[n];
-    double s;
-    z[n] = softplus_d(fma(w, q, net[H + n]), s);
-    zt[n] = s * w;
-  }
+    for (int n = 0; n < H; ++n) {
+      const double w = net[n];
+      double s;
+      z[n] = softplus_d(fma(w, q, net[H + n]), s);
+      zt[n] = s * w;
+    }
 #pragma unroll
-  for (int k = 1; k < L; ++k) {
-    const double* Wz = net + 2 * H + (k - 1) * stride;
+    for (int n = 0; n < H; ++n) {
+      pN = fma(net[owz + n], z[n], pN);
+      pD = fma(net[owz + n], zt[n], pD);
+    }
+  } else {
+    double z[H], zt[H];
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+      const double w = net[n];
+      double s;
+      z[n] = softplus_d(fma(w, q, net[H + n]), s);
+      zt[n] = s * w;
+    }
+#pragma unroll
+    for (int k = 1; k < L - 1; ++k) {
+      const double* Wz = net + 2 * H + (k - 1) * stride;
+      const double* Wx = Wz + H * H;
+      const double* b = Wx + H;
+      double zn[H], ztn[H];
+#pragma unroll
+      for (int n = 0; n < H; ++n) {
+        double acc = fma(Wx[n], q, b[n]);
+        double acct = Wx[n];
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+          acc = fma(Wz[n * H + m], z[m], acc);
+          acct = fma(Wz[n * H + m], zt[m], acct);
+        }
+        double s;
+        zn[n] = softplus_d(acc, s);
+        ztn[n] = s * acct;
+      }
+#pragma unroll
+      for (int n = 0; n < H; ++n) {
+        z[n] = zn[n];
+        zt[n] = ztn[n];
+      }
+    }
+    // last hidden layer: one neuron per iteration of a rolled loop, so its
+    // weight row is loaded when needed rather than held in registers, and its
+    // activation goes straight into the output sums
+    const double* Wz = net + 2 * H + (L - 2) * stride;
     const double* Wx = Wz + H * H;
     const double* b = Wx + H;
-    double zn[H], ztn[H];
-#pragma unroll
+#pragma unroll 1
     for (int n = 0; n < H; ++n) {
       double acc = fma(Wx[n], q, b[n]);
       double acct = Wx[n];
@@ -48,20 +91,10 @@ __device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net
         acct = fma(Wz[n * H + m], zt[m], acct);
       }
       double s;
-      zn[n] = softplus_d(acc, s);
-      ztn[n] = s * acct;
+      const double zv = softplus_d(acc, s);
+      pN = fma(net[owz + n], zv, pN);
+      pD = fma(net[owz + n], s * acct, pD);
     }
-#pragma unroll
-    for (int n = 0; n < H; ++n) {
-      z[n] = zn[n];
-      zt[n] = ztn[n];
-    }
-  }
-  double pN = 0.0, pD = 0.0;
-#pragma unroll
-  for (int n = 0; n < H; ++n) {
-    pN = fma(net[owz + n], z[n], pN);
-    pD = fma(net[owz + n], zt[n], pD);
   }
   const double wx = net[owz + H];
   dN = pD + wx;
@@ -81,21 +114,59 @@ __device__ __forceinline__ float yield_eval_lane_f32(const double* __restrict__ 
     s = (t >= 0.0f) ? inv : e * inv;
     return fmaxf(t, 0.0f) + __logf(1.0f + e);
   };
-  float z[H], zt[H];
+  float pN = 0.0f, pD = 0.0f;
+  if constexpr (L == 1) {
+    float z[H], zt[H];
 #pragma unroll
-  for (int n = 0; n < H; ++n) {
-    const float w = (float)net[n];
-    float s;
-    z[n] = sp(fmaf(w, q, (float)net[H + n]), s);
-    zt[n] = s * w;
-  }
+    for (int n = 0; n < H; ++n) {
+      const float w = (float)net[n];
+      float s;
+      z[n] = sp(fmaf(w, q, (float)net[H + n]), s);
+      zt[n] = s * w;
+    }
 #pragma unroll
-  for (int k = 1; k < L; ++k) {
-    const double* Wz = net + 2 * H + (k - 1) * stride;
+    for (int n = 0; n < H; ++n) {
+      pN = fmaf((float)net[owz + n], z[n], pN);
+      pD = fmaf((float)net[owz + n], zt[n], pD);
+    }
+  } else {
+    float z[H], zt[H];
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+      const float w = (float)net[n];
+      float s;
+      z[n] = sp(fmaf(w, q, (float)net[H + n]), s);
+      zt[n] = s * w;
+    }
+#pragma unroll
+    for (int k = 1; k < L - 1; ++k) {
+      const double* Wz = net + 2 * H + (k - 1) * stride;
+      const double* Wx = Wz + H * H;
+      const double* b = Wx + H;
+      float zn[H], ztn[H];
+#pragma unroll
+      for (int n = 0; n < H; ++n) {
+        float acc = fmaf((float)Wx[n], q, (float)b[n]);
+        float acct = (float)Wx[n];
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+          acc = fmaf((float)Wz[n * H + m], z[m], acc);
+          acct = fmaf((float)Wz[n * H + m], zt[m], acct);
+        }
+        float s;
+        zn[n] = sp(acc, s);
+        ztn[n] = s * acct;
+      }
+#pragma unroll
+      for (int n = 0; n < H; ++n) {
+        z[n] = zn[n];
+        zt[n] = ztn[n];
+      }
+    }
+    const double* Wz = net + 2 * H + (L - 2) * stride;
     const double* Wx = Wz + H * H;
     const double* b = Wx + H;
-    float zn[H], ztn[H];
-#pragma unroll
+#pragma unroll 1
     for (int n = 0; n < H; ++n) {
       float acc = fmaf((float)Wx[n], q, (float)b[n]);
       float acct = (float)Wx[n];
@@ -105,20 +176,10 @@ __device__ __forceinline__ float yield_eval_lane_f32(const double* __restrict__ 
         acct = fmaf((float)Wz[n * H + m], zt[m], acct);
       }
       float s;
-      zn[n] = sp(acc, s);
-      ztn[n] = s * acct;
+      const float zv = sp(acc, s);
+      pN = fmaf((float)net[owz + n], zv, pN);
+      pD = fmaf((float)net[owz + n], s * acct, pD);
     }
-#pragma unroll
-    for (int n = 0; n < H; ++n) {
-      z[n] = zn[n];
-      zt[n] = ztn[n];
-    }
-  }
-  float pN = 0.0f, pD = 0.0f;
-#pragma unroll
-  for (int n = 0; n < H; ++n) {
-    pN = fmaf((float)net[owz + n], z[n], pN);
-    pD = fmaf((float)net[owz + n], zt[n], pD);
   }
   const float wx = (float)net[owz + H];
   dN = pD + wx;
@@ -129,7 +190,7 @@ __device__ __forceinline__ float yield_eval_lane_f32(const double* __restrict__ 
 constexpr int kF32Iters = 12;
 
 template <int YH, int YL>
-__global__ __launch_bounds__(256) void history_kernel(HistArgs a) {
+__global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs a) {
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= a.nq) return;
   const Material M = a.m;
