@@ -10,6 +10,9 @@
 // A = weights (each wave keeps its 16-row slice, forward and transposed, in
 // registers for the whole persistent block); B = activations staged in LDS as
 // [qp][neuron] rows, so a lane's 8-element K slice is one 16-byte load.
+// Blocks of 4 waves at 4 waves per SIMD: the backward-pass state of the middle
+// layers lives in LDS and layer 0's Jacobian is re-read from the staged input
+// weights, which keeps the kernel within 128 registers.
 #include "device_common.h"
 #include "gedmg_internal.h"
 
@@ -57,7 +60,11 @@ struct LpCfg {
   // each) and wz: 6L + 1 fields of H
   static constexpr int NF = 6 * L + 1;
   static constexpr int C_BYTES = NF * H * 4;
-  static constexpr int LDS_BYTES = (Z_BYTES > RED_BYTES ? Z_BYTES : RED_BYTES) + X_BYTES + C_BYTES;
+  // backward-pass state of the middle layers 1 .. L-2: per wave, the logistic
+  // pair and the input Jacobian (5 fields) of each of a lane's 4 rows,
+  // lane-contiguous
+  static constexpr int ST_BYTES = (L > 2 ? L - 2 : 0) * WAVES * 5 * 4 * 64 * 4;
+  static constexpr int LDS_BYTES = (Z_BYTES > RED_BYTES ? Z_BYTES : RED_BYTES) + X_BYTES + C_BYTES + ST_BYTES;
   static_assert(WAVES % NT == 0, "waves must cover the neuron tiles");
 };
 
@@ -67,7 +74,7 @@ __device__ __forceinline__ T from_bits(uint16_t b) {
 }
 
 template <typename T, int H, int L, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
+__global__ __launch_bounds__(WAVES * 64, 4) void jet_lp_kernel(JetArgs a) {
   using C = LpCfg<H, L, WAVES>;
   using V8 = typename Lp<T>::v8;
   using V4 = typename Lp<T>::v4;
@@ -77,6 +84,7 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
   float* red = reinterpret_cast<float*>(lds_raw);
   float* xs = reinterpret_cast<float*>(lds_raw + (C::Z_BYTES > C::RED_BYTES ? C::Z_BYTES : C::RED_BYTES));
   float* cf = xs + QB * 3;  // [field][neuron]
+  float* st = cf + C::NF * H;  // [layer-1][wave][field][row][lane]
   const NetLayout lay = make_layout_hd(3, H, L, 3);
   const double* __restrict__ net = a.net;
 
@@ -108,7 +116,7 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
       v = net[lay.W0 + n * 3 + (f - 3 * L)];
     } else if (f < 6 * L) {
       const int k = 1 + (f - 3 * L - 3) / 3, i = (f - 3 * L - 3) % 3;
-      v = net[lay.Wx[k] + n * 3 + i];
+      v = net[(k == 1 ? lay.Wx[1] : lay.Wx[2]) + n * 3 + i];
     } else {
       v = net[lay.wz + n];
     }
@@ -121,16 +129,25 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
   __syncthreads();
 
   const int nbatch = (a.nq + QB - 1) / QB;
+  // the next tile's inputs travel in a register of the first QB * 3 threads
+  static_assert(QB * 3 <= WAVES * 64, "one input value per thread");
+  const int xi = threadIdx.x;
+  float xnext = 0.0f;
+  if (xi < QB * 3 && (long)blockIdx.x * QB + xi / 3 < a.nq) xnext = (float)a.x[(long)blockIdx.x * QB * 3 + xi];
   for (int batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
     const long q0 = (long)batch * QB;
-    for (int idx = threadIdx.x; idx < QB * 3; idx += blockDim.x)
-      xs[idx] = (q0 + idx / 3 < a.nq) ? (float)a.x[q0 * 3 + idx] : 0.0f;
+    if (xi < QB * 3) xs[xi] = xnext;
+    {
+      const long q1 = (long)(batch + gridDim.x) * QB;
+      xnext = 0.0f;
+      if (xi < QB * 3 && q1 + xi / 3 < a.nq) xnext = (float)a.x[q1 * 3 + xi];
+    }
     __syncthreads();
     const float x[3] = {xs[j * 3], xs[j * 3 + 1], xs[j * 3 + 2]};
 
     // State kept for the backward pass: layers 0 .. L-2 (the last hidden
     // layer's adjoint is wz, so its Hessian term is added in the forward pass).
-    float sS[L][4], sB[L][4], Jt[L][4][3], dz[4], zt[4][3];
+    float s0r[4], sb0r[4], dz[4], zt[4][3];
     float part[10];
 #pragma unroll
     for (int t = 0; t < 10; ++t) part[t] = 0.f;
@@ -141,18 +158,18 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
       const int n = nt * 16 + 4 * lg + r;
       const float w0 = cf[(3 * L) * H + n], w1 = cf[(3 * L + 1) * H + n], w2 = cf[(3 * L + 2) * H + n];
       const float da = w0 * x[0] + w1 * x[1] + w2 * x[2];
-      dz[r] = delta_softplus(da, cf[n], cf[H + n], cf[2 * H + n], sS[0][r], sB[0][r]);
-      Jt[0][r][0] = w0; Jt[0][r][1] = w1; Jt[0][r][2] = w2;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) zt[r][i] = sS[0][r] * Jt[0][r][i];
+      dz[r] = delta_softplus(da, cf[n], cf[H + n], cf[2 * H + n], s0r[r], sb0r[r]);
+      zt[r][0] = s0r[r] * w0;
+      zt[r][1] = s0r[r] * w1;
+      zt[r][2] = s0r[r] * w2;
       if (L == 1) {
         const float wz = cf[6 * L * H + n];
         part[0] += wz * dz[r];
 #pragma unroll
         for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
-        abar[r] = wz * sS[0][r];
+        abar[r] = wz * s0r[r];
         if (hess) {
-          const float c2 = abar[r] * sB[0][r];
+          const float c2 = abar[r] * sb0r[r];
           part[4] += c2 * w0 * w0;
           part[5] += c2 * w1 * w1;
           part[6] += c2 * w2 * w2;
@@ -218,11 +235,12 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
             part[8] += c2 * jk[0] * jk[2];
             part[9] += c2 * jk[1] * jk[2];
           }
-        } else {
-          sS[k][r] = s_;
-          sB[k][r] = sb_;
+        } else if (hess) {
+          float* stk = st + ((size_t)(k - 1) * WAVES + wave) * 5 * 4 * 64 + lane;
+          stk[(0 * 4 + r) * 64] = s_;
+          stk[(1 * 4 + r) * 64] = sb_;
 #pragma unroll
-          for (int i = 0; i < 3; ++i) Jt[k][r][i] = jk[i];
+          for (int i = 0; i < 3; ++i) stk[((2 + i) * 4 + r) * 64] = jk[i];
         }
       }
     }
@@ -243,9 +261,22 @@ __global__ __launch_bounds__(WAVES * 64) void jet_lp_kernel(JetArgs a) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          abar[r] = acc[r] * sS[k - 1][r];
-          const float c2 = abar[r] * sB[k - 1][r];
-          const float* Jr = Jt[k - 1][r];
+          float sv, sbv, Jr[3];
+          if (k - 1 == 0) {
+            const int n = nt * 16 + 4 * lg + r;
+            sv = s0r[r];
+            sbv = sb0r[r];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Jr[i] = cf[(3 * L + i) * H + n];
+          } else {
+            const float* stk = st + ((size_t)(k - 2) * WAVES + wave) * 5 * 4 * 64 + lane;
+            sv = stk[(0 * 4 + r) * 64];
+            sbv = stk[(1 * 4 + r) * 64];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Jr[i] = stk[((2 + i) * 4 + r) * 64];
+          }
+          abar[r] = acc[r] * sv;
+          const float c2 = abar[r] * sbv;
           part[4] += c2 * Jr[0] * Jr[0];
           part[5] += c2 * Jr[1] * Jr[1];
           part[6] += c2 * Jr[2] * Jr[2];
@@ -284,15 +315,16 @@ template <typename T, int H, int L, int WAVES>
 static hipError_t launch_lp(const JetArgs& a, hipStream_t s, int num_cu) {
   using C = LpCfg<H, L, WAVES>;
   const int nbatch = (a.nq + C::QB - 1) / C::QB;
-  int per_cu = (160 * 1024) / C::LDS_BYTES;
-  if (per_cu > 4) per_cu = 4;
+  hipError_t e = hipFuncSetAttribute((const void*)jet_lp_kernel<T, H, L, WAVES>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jet_lp_kernel<T, H, L, WAVES>, WAVES * 64, C::LDS_BYTES);
+  if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   int grid = num_cu * per_cu;
   if (grid > nbatch) grid = nbatch;
   if (grid <= 0) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute((const void*)jet_lp_kernel<T, H, L, WAVES>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((jet_lp_kernel<T, H, L, WAVES>), dim3(grid), dim3(WAVES * 64), C::LDS_BYTES, s, a);
   return hipGetLastError();
 }
@@ -306,9 +338,9 @@ static hipError_t dispatch(int H, const JetArgs& a, hipStream_t s, int num_cu) {
     case 321: return launch_lp<T, 32, 1, 4>(a, s, num_cu);
     case 322: return launch_lp<T, 32, 2, 4>(a, s, num_cu);
     case 323: return launch_lp<T, 32, 3, 4>(a, s, num_cu);
-    case 641: return launch_lp<T, 64, 1, 8>(a, s, num_cu);
-    case 642: return launch_lp<T, 64, 2, 8>(a, s, num_cu);
-    case 643: return launch_lp<T, 64, 3, 8>(a, s, num_cu);
+    case 641: return launch_lp<T, 64, 1, 4>(a, s, num_cu);
+    case 642: return launch_lp<T, 64, 2, 4>(a, s, num_cu);
+    case 643: return launch_lp<T, 64, 3, 4>(a, s, num_cu);
     default: return hipErrorInvalidValue;
   }
 }
