@@ -1,7 +1,12 @@
 // Global Newton step of the monolithic scheme (Sec. 3.2: history updated in
 // every global iteration, tangent contributions of kappa included; each step
 // starts from the caller's predictor built on the last converged solution)
-// with a Jacobi-preconditioned Krylov solve per iteration.
+// with a preconditioned Krylov solve per iteration.  The CG preconditioner is
+// Jacobi plus a one-vector coarse correction on the uniform damage field
+// (M^-1 r = D^-1 r + chi (chi . r) / (chi . K chi), chi = 1 on the free damage
+// dofs): once the points yield, the damage block's only stiffness against a
+// uniform phi is beta_d (1 - d kappa / d phi), orders of magnitude below the
+// rest of the spectrum, and this mode would otherwise set the CG iteration count.
 //
 // Sparse kernels are deterministic: fixed grids, per-block partial sums in a
 // fixed order, one-block final reductions; Krylov scalars stay on the device
@@ -19,8 +24,13 @@ constexpr int kRedBlocks = 512;  // blocks of every reduction kernel
 constexpr int kThreads = 256;
 
 // Device scalar slots (doubles).
+// S_FLAG + 1 holds sums read back by the host; S_E = chi . K chi and S_CC =
+// (chi . r) / S_E, the coarse coefficient of the current residual.
 enum Slot { S_RZ = 0, S_PAP, S_ALPHA, S_BETA, S_RR, S_BB, S_RHO, S_OMEGA, S_TT, S_TS, S_VR, S_RZNEW,
-            S_FLAG, S_NSLOTS = 16 };
+            S_FLAG, S_E = 14, S_CC = 15, S_NSLOTS = 16 };
+
+// chi_i: free (not Dirichlet) damage dof
+__device__ __forceinline__ bool chi(long i, int nd, const uint8_t* mask) { return (i % nd) == nd - 1 && !mask[i]; }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
 #pragma unroll
@@ -175,35 +185,99 @@ __global__ void reduce_kernel(const double* part, double* scal, int slot, int sl
 
 // ---- CG pieces.  r.z alternates between two slots (ra holds the current
 // value, rb receives the next), so every block forms alpha and beta itself and
-// no single-thread scalar kernel sits between the vector kernels.
-__global__ void cg_update_kernel(double* x, double* r, double* z, const double* p, const double* Ap,
-                                 const double* dinv, double* scal, int ra, long n, double* part) {
+// no single-thread scalar kernel sits between the vector kernels.  z = M^-1 r
+// is never stored: r.z = r.D^-1.r + (chi.r)^2 / E comes out of the partial
+// sums, and the p update forms z on the fly.
+
+// chi . K chi over the masked matrix (rows and columns of free damage dofs)
+__global__ void coarse_energy_kernel(const double* K, const int32_t* rowptr, const int32_t* col,
+                                     const uint8_t* mask, int nd, long nrows, double* part) {
+  __shared__ double sh[8];
+  double acc = 0.0;
+  for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (long)gridDim.x * blockDim.x) {
+    if (!chi(r, nd, mask)) continue;
+    for (int j = rowptr[r]; j < rowptr[r + 1]; ++j)
+      if (chi(col[j], nd, mask)) acc += K[j];
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// partial sums of r.D^-1.r, r.r and chi.r
+__global__ void cg_init_kernel(const double* r, const double* dinv, const uint8_t* mask, int nd, long n,
+                               double* part) {
+  __shared__ double sh[8];
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double ri = r[i];
+    s1 += ri * dinv[i] * ri;
+    s2 += ri * ri;
+    if (chi(i, nd, mask)) s3 += ri;
+  }
+  double t = block_sum(s1, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  t = block_sum(s2, sh);
+  if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = t;
+  t = block_sum(s3, sh);
+  if (threadIdx.x == 0) part[2 * kRedBlocks + blockIdx.x] = t;
+}
+
+__global__ void cg_update_kernel(double* x, double* r, const double* p, const double* Ap, const double* dinv,
+                                 const uint8_t* mask, int nd, double* scal, int ra, long n, double* part) {
   __shared__ double sh[8];
   const double pap = scal[S_PAP];
   const double alpha = (pap > 0.0) ? scal[ra] / pap : 0.0;
   if (!(pap > 0.0) && blockIdx.x == 0 && threadIdx.x == 0) scal[S_FLAG] = 1.0;  // non-positive curvature
-  double s1 = 0.0, s2 = 0.0;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * Ap[i];
     r[i] = ri;
-    const double zi = dinv[i] * ri;
-    z[i] = zi;
-    s1 += ri * zi;
+    s1 += ri * dinv[i] * ri;
     s2 += ri * ri;
+    if (chi(i, nd, mask)) s3 += ri;
   }
-  const double t1 = block_sum(s1, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t1;
-  const double t2 = block_sum(s2, sh);
-  if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = t2;
+  double t = block_sum(s1, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  t = block_sum(s2, sh);
+  if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = t;
+  t = block_sum(s3, sh);
+  if (threadIdx.x == 0) part[2 * kRedBlocks + blockIdx.x] = t;
 }
 
-// p = z + beta p with beta = (r.z)_new / (r.z)
-__global__ void cg_p_kernel(double* p, const double* z, const double* scal, int ra, int rb, long n) {
+// One block: scal[S_CC] = (chi.r) / E (0 when E is not positive), scal[srz] =
+// r.D^-1.r + S_CC (chi.r), scal[S_RR] = r.r.
+__global__ void cg_reduce_kernel(const double* part, double* scal, int srz) {
+  __shared__ double sh[8];
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) {
+    s1 += part[i];
+    s2 += part[kRedBlocks + i];
+    s3 += part[2 * kRedBlocks + i];
+  }
+  const double t1 = block_sum(s1, sh);
+  const double t2 = block_sum(s2, sh);
+  const double t3 = block_sum(s3, sh);
+  if (threadIdx.x == 0) {
+    const double E = scal[S_E];
+    const double cc = (E > 0.0) ? t3 / E : 0.0;
+    scal[S_CC] = cc;
+    scal[srz] = t1 + cc * t3;
+    scal[S_RR] = t2;
+  }
+}
+
+// p = z + beta p, z = D^-1 r + S_CC chi, beta = (r.z)_new / (r.z); first = 1
+// starts the recurrence (beta = 0)
+__global__ void cg_p_kernel(double* p, const double* r, const double* dinv, const uint8_t* mask, int nd,
+                            const double* scal, int ra, int rb, int first, long n) {
   const double rz = scal[ra];
-  const double beta = (rz != 0.0) ? scal[rb] / rz : 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
+  const double beta = (!first && rz != 0.0) ? scal[rb] / rz : 0.0;
+  const double cc = scal[S_CC];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double zi = dinv[i] * r[i] + (chi(i, nd, mask) ? cc : 0.0);
+    p[i] = first ? zi : zi + beta * p[i];
+  }
 }
 
 __global__ void precond_kernel(double* z, const double* r, const double* dinv, long n) {
@@ -357,7 +431,7 @@ int ensure_work(gedmg_ctx* c, Work** out) {
       al(&w.z, w.ndof) || al(&w.p, w.ndof) || al(&w.q, w.ndof) || al(&w.v, w.ndof) ||
       al(&w.t, w.ndof) || al(&w.r0, w.ndof) || al(&w.dinv, w.ndof) ||
       al(&w.ub, (long)c->dim * c->n_nodes) || al(&w.phib, c->n_nodes) ||
-      al(&w.part, 2 * kRedBlocks) || al(&w.scal, S_NSLOTS) ||
+      al(&w.part, 3 * kRedBlocks) || al(&w.scal, S_NSLOTS) ||
       hipMalloc((void**)&w.mask, std::max(w.ndof, 1L)) ||
       hipHostMalloc((void**)&w.hscal, sizeof(double) * S_NSLOTS, 0)) {
     c->err = "device allocation for the Newton workspace failed";
@@ -402,21 +476,28 @@ int read_scalars(gedmg_ctx* c, Work& w) {
   return GEDMG_OK;
 }
 
-// Solve K x = b (Jacobi-preconditioned CG; BiCGStab on non-positive curvature).
-// Returns iterations in *its.
+// Solve K x = b (CG with the Jacobi + coarse preconditioner; BiCGStab with
+// Jacobi on non-positive curvature).  K is the masked matrix and w.mask the
+// Dirichlet mask of this solve.  Returns iterations in *its.
 int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int* its) {
   const long n = w.ndof;
   const int gr = kRedBlocks;
+  const int nd = c->dim + 1;
   int rc;
   *its = 0;
   GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
   GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
   GH(hipMemcpyAsync(w.r, w.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-  hipLaunchKernelGGL(precond_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.z, w.r, w.dinv, n);
-  if ((rc = dot2(c, w, w.r, w.z, w.b, w.b, S_RZ, S_BB))) return rc;
-  GH(hipMemcpyAsync(w.p, w.z, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL(coarse_energy_kernel, dim3(gr), dim3(kThreads), 0, c->stream, K, c->drowptr, c->dcol,
+                     w.mask, nd, n, w.part);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_E, -1);
+  hipLaunchKernelGGL(cg_init_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.r, w.dinv, w.mask, nd, n, w.part);
+  hipLaunchKernelGGL(cg_reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_RZ);
+  hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.dinv, w.mask, nd, w.scal,
+                     S_RZ, S_RZ, 1, n);
+  GH(hipGetLastError());
   if ((rc = read_scalars(c, w))) return rc;
-  const double bb = w.hscal[S_BB];
+  const double bb = w.hscal[S_RR];
   if (bb == 0.0) return GEDMG_OK;
   if (!std::isfinite(bb)) { c->err = "non-finite right-hand side"; return GEDMG_E_NONFINITE; }
   const double tol2 = rtol * rtol * bb;
@@ -425,10 +506,11 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
   for (int it = 1; it <= max_it; ++it) {
     const int ra = (it & 1) ? S_RZ : S_RZNEW, rb = (it & 1) ? S_RZNEW : S_RZ;
     if ((rc = spmv(c, w, K, w.p, w.q, w.p, S_PAP))) return rc;
-    hipLaunchKernelGGL(cg_update_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.x, w.r, w.z, w.p, w.q,
-                       w.dinv, w.scal, ra, n, w.part);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, rb, S_RR);
-    hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.z, w.scal, ra, rb, n);
+    hipLaunchKernelGGL(cg_update_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.x, w.r, w.p, w.q, w.dinv,
+                       w.mask, nd, w.scal, ra, n, w.part);
+    hipLaunchKernelGGL(cg_reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, rb);
+    hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.dinv, w.mask, nd, w.scal,
+                       ra, rb, 0, n);
     GH(hipGetLastError());
     *its = it;
     if (it % check == 0 || it == max_it) {
