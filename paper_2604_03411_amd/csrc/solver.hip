@@ -222,12 +222,28 @@ __global__ void cg_init_kernel(const double* r, const double* dinv, const uint8_
   if (threadIdx.x == 0) part[2 * kRedBlocks + blockIdx.x] = t;
 }
 
+// Every block sums the SpMV kernel's partials of p.Ap itself (same order in
+// every block, so all blocks get the same alpha); block 0 publishes it.
+__device__ __forceinline__ double block_total(const double* part, double* sh, double* bc) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) s += part[i];
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) *bc = t;
+  __syncthreads();
+  return *bc;
+}
+
 __global__ void cg_update_kernel(double* x, double* r, const double* p, const double* Ap, const double* dinv,
-                                 const uint8_t* mask, int nd, double* scal, int ra, long n, double* part) {
+                                 const uint8_t* mask, int nd, double* scal, int ra, long n,
+                                 const double* part_pap, double* part) {
   __shared__ double sh[8];
-  const double pap = scal[S_PAP];
+  __shared__ double bc;
+  const double pap = block_total(part_pap, sh, &bc);
   const double alpha = (pap > 0.0) ? scal[ra] / pap : 0.0;
-  if (!(pap > 0.0) && blockIdx.x == 0 && threadIdx.x == 0) scal[S_FLAG] = 1.0;  // non-positive curvature
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[S_PAP] = pap;
+    if (!(pap > 0.0)) scal[S_FLAG] = 1.0;  // non-positive curvature
+  }
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     x[i] += alpha * p[i];
@@ -245,10 +261,15 @@ __global__ void cg_update_kernel(double* x, double* r, const double* p, const do
   if (threadIdx.x == 0) part[2 * kRedBlocks + blockIdx.x] = t;
 }
 
-// One block: scal[S_CC] = (chi.r) / E (0 when E is not positive), scal[srz] =
-// r.D^-1.r + S_CC (chi.r), scal[S_RR] = r.r.
-__global__ void cg_reduce_kernel(const double* part, double* scal, int srz) {
+// p = z + beta p, z = D^-1 r + cc chi, beta = (r.z)_new / (r.z); first = 1
+// starts the recurrence (beta = 0).  Every block sums the three partial
+// arrays of the update kernel itself (same order everywhere): cc = (chi.r)/E,
+// (r.z)_new = r.D^-1.r + cc (chi.r); block 0 publishes them in scal[S_CC],
+// scal[rb] and r.r in scal[S_RR].
+__global__ void cg_p_kernel(double* p, const double* r, const double* dinv, const uint8_t* mask, int nd,
+                            const double* part, double* scal, int ra, int rb, int first, long n) {
   __shared__ double sh[8];
+  __shared__ double bc[3];
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) {
     s1 += part[i];
@@ -259,21 +280,21 @@ __global__ void cg_reduce_kernel(const double* part, double* scal, int srz) {
   const double t2 = block_sum(s2, sh);
   const double t3 = block_sum(s3, sh);
   if (threadIdx.x == 0) {
-    const double E = scal[S_E];
-    const double cc = (E > 0.0) ? t3 / E : 0.0;
-    scal[S_CC] = cc;
-    scal[srz] = t1 + cc * t3;
-    scal[S_RR] = t2;
+    bc[0] = t1;
+    bc[1] = t2;
+    bc[2] = t3;
   }
-}
-
-// p = z + beta p, z = D^-1 r + S_CC chi, beta = (r.z)_new / (r.z); first = 1
-// starts the recurrence (beta = 0)
-__global__ void cg_p_kernel(double* p, const double* r, const double* dinv, const uint8_t* mask, int nd,
-                            const double* scal, int ra, int rb, int first, long n) {
+  __syncthreads();
+  const double E = scal[S_E];
+  const double cc = (E > 0.0) ? bc[2] / E : 0.0;
+  const double rz_new = bc[0] + cc * bc[2];
   const double rz = scal[ra];
-  const double beta = (!first && rz != 0.0) ? scal[rb] / rz : 0.0;
-  const double cc = scal[S_CC];
+  const double beta = (!first && rz != 0.0) ? rz_new / rz : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[S_CC] = cc;
+    scal[rb] = rz_new;
+    scal[S_RR] = bc[1];
+  }
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const double zi = dinv[i] * r[i] + (chi(i, nd, mask) ? cc : 0.0);
     p[i] = first ? zi : zi + beta * p[i];
@@ -431,7 +452,7 @@ int ensure_work(gedmg_ctx* c, Work** out) {
       al(&w.z, w.ndof) || al(&w.p, w.ndof) || al(&w.q, w.ndof) || al(&w.v, w.ndof) ||
       al(&w.t, w.ndof) || al(&w.r0, w.ndof) || al(&w.dinv, w.ndof) ||
       al(&w.ub, (long)c->dim * c->n_nodes) || al(&w.phib, c->n_nodes) ||
-      al(&w.part, 3 * kRedBlocks) || al(&w.scal, S_NSLOTS) ||
+      al(&w.part, 4 * kRedBlocks) || al(&w.scal, S_NSLOTS) ||
       hipMalloc((void**)&w.mask, std::max(w.ndof, 1L)) ||
       hipHostMalloc((void**)&w.hscal, sizeof(double) * S_NSLOTS, 0)) {
     c->err = "device allocation for the Newton workspace failed";
@@ -458,6 +479,19 @@ int spmv(gedmg_ctx* c, Work& w, const double* K, const double* x, double* y, con
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, slot, -1);
     GH(hipGetLastError());
   }
+  return GEDMG_OK;
+}
+
+// y = K x and per-block partials of wv . y into part (no reduction launch)
+int spmv_part(gedmg_ctx* c, Work& w, const double* K, const double* x, double* y, const double* wv, double* part) {
+  const int G = c->dim == 3 ? 32 : 16;
+  if (G == 32)
+    hipLaunchKernelGGL((spmv_dot_kernel<32>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, K, c->drowptr,
+                       c->dcol, x, y, wv, w.ndof, part);
+  else
+    hipLaunchKernelGGL((spmv_dot_kernel<16>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, K, c->drowptr,
+                       c->dcol, x, y, wv, w.ndof, part);
+  GH(hipGetLastError());
   return GEDMG_OK;
 }
 
@@ -492,9 +526,8 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
                      w.mask, nd, n, w.part);
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_E, -1);
   hipLaunchKernelGGL(cg_init_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.r, w.dinv, w.mask, nd, n, w.part);
-  hipLaunchKernelGGL(cg_reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_RZ);
-  hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.dinv, w.mask, nd, w.scal,
-                     S_RZ, S_RZ, 1, n);
+  hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.dinv, w.mask, nd, w.part,
+                     w.scal, S_RZ, S_RZ, 1, n);
   GH(hipGetLastError());
   if ((rc = read_scalars(c, w))) return rc;
   const double bb = w.hscal[S_RR];
@@ -502,22 +535,39 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
   if (!std::isfinite(bb)) { c->err = "non-finite right-hand side"; return GEDMG_E_NONFINITE; }
   const double tol2 = rtol * rtol * bb;
   const int check = 8;
+  // CG polls the residual adaptively: each poll stalls the stream, so the next
+  // one is placed at 70 % of the iterations the observed decay rate still needs
+  // (between 8 and 128 iterations ahead)
+  int next_poll = check, prev_it = 0;
+  double prev_rr = bb;
   bool use_bicg = false;
   for (int it = 1; it <= max_it; ++it) {
     const int ra = (it & 1) ? S_RZ : S_RZNEW, rb = (it & 1) ? S_RZNEW : S_RZ;
-    if ((rc = spmv(c, w, K, w.p, w.q, w.p, S_PAP))) return rc;
+    // three launches: q = K p with partials of p.q (kept apart from the
+    // update's partials), the update (alpha from those partials), the p update
+    double* part_pap = w.part + 3 * kRedBlocks;
+    if ((rc = spmv_part(c, w, K, w.p, w.q, w.p, part_pap))) return rc;
     hipLaunchKernelGGL(cg_update_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.x, w.r, w.p, w.q, w.dinv,
-                       w.mask, nd, w.scal, ra, n, w.part);
-    hipLaunchKernelGGL(cg_reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, rb);
-    hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.dinv, w.mask, nd, w.scal,
-                       ra, rb, 0, n);
+                       w.mask, nd, w.scal, ra, n, part_pap, w.part);
+    hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.dinv, w.mask, nd, w.part,
+                       w.scal, ra, rb, 0, n);
     GH(hipGetLastError());
     *its = it;
-    if (it % check == 0 || it == max_it) {
+    if (it == next_poll || it == max_it) {
       if ((rc = read_scalars(c, w))) return rc;
       if (w.hscal[S_FLAG] != 0.0) { use_bicg = true; break; }
-      if (!std::isfinite(w.hscal[S_RR])) { c->err = "non-finite Krylov residual"; return GEDMG_E_NONFINITE; }
-      if (w.hscal[S_RR] <= tol2) return GEDMG_OK;
+      const double rr = w.hscal[S_RR];
+      if (!std::isfinite(rr)) { c->err = "non-finite Krylov residual"; return GEDMG_E_NONFINITE; }
+      if (rr <= tol2) return GEDMG_OK;
+      int ahead = check;
+      if (rr > 0.0 && rr < prev_rr) {
+        const double rate = std::log(rr / prev_rr) / (it - prev_it);  // per iteration, < 0
+        const double need = std::log(tol2 / rr) / rate;
+        ahead = (int)std::min(128.0, std::max((double)check, 0.7 * need));
+      }
+      prev_rr = rr;
+      prev_it = it;
+      next_poll = it + ahead;
     }
   }
   if (!use_bicg) { c->err = "CG reached the iteration limit"; return GEDMG_E_LINSOLVE; }
