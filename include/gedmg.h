@@ -106,6 +106,11 @@ typedef struct {
   double newton_rtol;     /* ||R_f|| <= max(newton_rtol * max(1, ||R_f^0||), newton_atol) */
   double newton_atol;
   double krylov_rtol;     /* relative residual of each linear solve (default 1e-12) */
+  int32_t krylov_forcing; /* 1 (default): inexact Newton, iteration k solves to the relative residual
+                             max(krylov_rtol, min(1e-3, ||R_f^k|| / ||R_f^0||)), so early iterations do
+                             not pay for accuracy the Newton residual cannot use; 0: every solve to
+                             krylov_rtol.  The Newton test on the FP64 residual decides convergence
+                             either way. */
 } gedmg_solver_opts;
 
 typedef struct {

@@ -652,7 +652,7 @@ extern "C" int gedmg_adjoint(gedmg_ctx* c, int32_t n_steps, const gedmg_dirichle
     c->err = "yield-network width above 32 is not supported by the adjoint";
     return GEDMG_E_SHAPE;
   }
-  gedmg_solver_opts o{25, 20000, 100, 1e-10, 0.0, 1e-12};
+  gedmg_solver_opts o{25, 20000, 100, 1e-10, 0.0, 1e-12, 1};
   if (opts_in) o = *opts_in;
   gedmg_adjoint_report local{};
   gedmg_adjoint_report& R = rep ? *rep : local;

@@ -661,14 +661,17 @@ int solver_solve_free(gedmg_ctx* c, double* A, const gedmg_dirichlet* bc, const 
   GH(hipMemcpyAsync(x, w.x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
   // iterative refinement on the true FP64 residual: the Krylov recurrence
   // residual drifts from b - Ax, and without an outer Newton loop the
-  // solution keeps the error cond(A) * rtol
+  // solution keeps the error cond(A) * rtol.  A correction only has to remove
+  // that drift, so each pass solves to max(rtol, 1e-3) of its own residual
+  // (three orders per pass).
+  const double rtol_pass = std::max(rtol, 1e-3);
   for (int pass = 0; pass < refine; ++pass) {
     if ((rc = spmv(c, w, A, x, w.q, nullptr, -1))) return rc;
     hipLaunchKernelGGL(masked_residual_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, rhs, w.q, w.mask,
                        w.b, n);
     GH(hipGetLastError());
     int more = 0;
-    if ((rc = krylov(c, w, A, max_it, rtol, &more))) return rc;
+    if ((rc = krylov(c, w, A, max_it, rtol_pass, &more))) return rc;
     *its += more;
     hipLaunchKernelGGL(add_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, x, w.x, n);
     GH(hipGetLastError());
@@ -692,7 +695,7 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
     c->err = "unknown precision";
     return GEDMG_E_ARG;
   }
-  gedmg_solver_opts o{25, 20000, 100, 1e-10, 0.0, 1e-12};
+  gedmg_solver_opts o{25, 20000, 100, 1e-10, 0.0, 1e-12, 1};
   if (opts_in) o = *opts_in;
   if (o.max_local <= 0 || o.max_newton < 0 || o.max_krylov <= 0) {
     c->err = "solver limits must be positive";
@@ -777,7 +780,9 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
                        c->dcol, w.mask, w.dinv, n);
     GH(hipGetLastError());
     int its = 0;
-    rc = krylov(c, w, w.K, o.max_krylov, o.krylov_rtol, &its);
+    const double eta =
+        o.krylov_forcing ? std::max(o.krylov_rtol, std::min(1e-3, res / std::max(res0, 1e-300))) : o.krylov_rtol;
+    rc = krylov(c, w, w.K, o.max_krylov, eta, &its);
     r.krylov_iters_total += its;
     if (rc) return rollback(rc);
     hipLaunchKernelGGL(update_fields_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, u, phi, w.x,

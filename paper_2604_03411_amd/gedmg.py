@@ -54,7 +54,8 @@ class Dirichlet(C.Structure):
 
 class SolverOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("max_krylov", C.c_int32), ("max_local", C.c_int32),
-                ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("krylov_rtol", C.c_double)]
+                ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("krylov_rtol", C.c_double),
+                ("krylov_forcing", C.c_int32)]
 
 
 class NewtonReport(C.Structure):
@@ -253,13 +254,14 @@ class Context:
 
     def newton_step(self, u, phi, kappa, bc_dofs, bc_vals, precision="fp64", reaction_dofs=None,
                     max_newton=25, max_krylov=20000, max_local=100, newton_rtol=1e-10,
-                    newton_atol=0.0, krylov_rtol=1e-12, raise_on_error=True):
+                    newton_atol=0.0, krylov_rtol=1e-12, krylov_forcing=True, raise_on_error=True):
         """One monolithic load step in place on (u, phi, kappa); returns the report as a dict."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         dofs = torch.as_tensor(np.asarray(bc_dofs, dtype=np.int32), device=self.dev).contiguous()
         vals = _f64(bc_vals, self.dev)
         bc = Dirichlet(int(dofs.numel()), C.c_void_p(dofs.data_ptr()), C.c_void_p(vals.data_ptr()))
-        opts = SolverOpts(max_newton, max_krylov, max_local, newton_rtol, newton_atol, krylov_rtol)
+        opts = SolverOpts(max_newton, max_krylov, max_local, newton_rtol, newton_atol, krylov_rtol,
+                          1 if krylov_forcing else 0)
         rd = None
         nr = 0
         if reaction_dofs is not None:
@@ -299,7 +301,8 @@ class Context:
         u, phi, kap = (_f64(t, dv).clone() for t in (path.u0, path.phi0, path.kappa0))
         o = path.opts
         opts = SolverOpts(o.get("max_newton", 25), o.get("max_krylov", 20000), o.get("max_local", 100),
-                          o.get("newton_rtol", 1e-10), o.get("newton_atol", 0.0), o.get("krylov_rtol", 1e-12))
+                          o.get("newton_rtol", 1e-10), o.get("newton_atol", 0.0), o.get("krylov_rtol", 1e-12),
+                          1 if o.get("krylov_forcing", True) else 0)
         ge = np.zeros(self._te.size)
         gy = np.zeros(self._ty.size)
         loss = C.c_double()
