@@ -94,13 +94,6 @@ __device__ __forceinline__ double exp_d(double t) {
   return ldexp(1.0 + q, (int)n);
 }
 
-__device__ __forceinline__ double expm1_nonpos(double t) {
-  double n;
-  const double q = expm1_reduced(t, n);
-  const int ni = (int)n;
-  return (n == 0.0) ? q : ldexp(q, ni) + (ldexp(1.0, ni) - 1.0);
-}
-
 __device__ __forceinline__ double log1p_small(double y) {
   const double s = div_d(y, 2.0 + y);
   const double z = s * s;
@@ -123,30 +116,7 @@ __device__ __forceinline__ double log1p_small(double y) {
   return fma(ts * z, p, ts);
 }
 
-// softplus(a) and the logistic pair (s, 1 - s) at a.
-__device__ __forceinline__ double softplus_pair(double a, double& s, double& sb) {
-  const double e = exp_d(-fabs(a));
-  const double inv = rcp_d(1.0 + e);
-  s = (a >= 0.0) ? inv : e * inv;
-  sb = (a >= 0.0) ? e * inv : inv;
-  return fmax(a, 0.0) + log1p_small(e);
-}
-
-// log(w) for w = 1 + y > 0, given both: y > -1/2 goes through the series in y
-// (relative precision of small y); otherwise w, which is then accurate, is
-// split as m 2^k with m in [3/4, 3/2) and log(w) = k ln2 + log1p(m - 1).
-__device__ __forceinline__ double log1p_pair(double y, double w) {
-  int k;
-  double m = frexp(w, &k);
-  const bool low = m < 0.75;
-  m = low ? 2.0 * m : m;
-  k = low ? k - 1 : k;
-  const bool small = y > -0.5;
-  const double f = small ? y : m - 1.0;
-  const double kk = small ? 0.0 : (double)k;
-  return fma(kk, kLn2Hi, fma(kk, kLn2Lo, log1p_small(f)));
-}
-
+// Increment form of the activations (used by the energy-network jets):
 // softplus(a0 + d) - softplus(a0) and the logistic pair (s, 1 - s) at
 // a = a0 + d, from s0 = logistic(a0) and sb0 = logistic(-a0), without branches.
 // For a <= 0 the increment is log(w) with w = sb0 + s0 e^d = 1 + s0 expm1(d);
@@ -154,23 +124,11 @@ __device__ __forceinline__ double log1p_pair(double y, double w) {
 // w = s0 + sb0 e^-d.  Choosing the form by the sign of a keeps the increment
 // free of cancellation (the logarithm carries the whole increment where the
 // network is in its flat half), w is a sum of non-negative terms, and the
-// logistic pair is (s0 e^d / w, sb0 / w) or (s0 / w, sb0 e^-d / w).
-__device__ __forceinline__ double delta_softplus(double d, double a0, double s0, double sb0, double& s,
-                                                 double& sb) {
-  const bool fa = a0 + d <= 0.0;
-  double n;
-  const double q = expm1_reduced(fa ? d : -d, n);
-  const int ni = (int)n;
-  const double E = ldexp(1.0 + q, ni);
-  const double M = (n == 0.0) ? q : ldexp(q, ni) + (ldexp(1.0, ni) - 1.0);
-  const double p = fa ? s0 : sb0, c = fa ? sb0 : s0;
-  const double w = fma(p, E, c);
-  const double inv = rcp_d(w);
-  const double sp = p * E * inv, sc = c * inv;
-  s = fa ? sp : sc;
-  sb = fa ? sc : sp;
-  return (fa ? 0.0 : d) + log1p_pair(p * M, w);
-}
+// logistic pair is (s0 e^d / w, sb0 / w) or (s0 / w, sb0 e^-d / w).  The
+// split also keeps the result exact where |d| exceeds the exponent range: with
+// a0 and a both large and positive (reference pre-activations of thousands
+// occur in deep networks with large weights), sb0 underflows and the a > 0
+// form returns d + log(s0) exactly, where the a <= 0 form alone would saturate.
 
 // ---- table-driven variants; the caller stages the kMathTabDoubles-entry table
 // (exp: 64 x (Thi, Tlo); log: 64 x (1/c, log c hi, log c lo, 0); built on the
@@ -234,7 +192,7 @@ __device__ __forceinline__ double log1p_tab(double y, double wacc, double winv, 
   return fma(0.0, y, res);  // keeps a NaN y
 }
 
-// delta_softplus with the table-driven exp / log1p.
+// The increment form above with the table-driven exp / log1p.
 __device__ __forceinline__ double delta_softplus_tab(double d, double a0, double s0, double sb0, double& s,
                                                      double& sb, const double* __restrict__ et,
                                                      const double* __restrict__ lt) {
