@@ -107,6 +107,7 @@ struct HistArgs {
   double yN0;            // yield network N(0)
   int yL;
   int max_local;
+  const double* mtab;    // exp / log tables of the table-driven FP64 functions (kMathTabDoubles)
 };
 
 // Mesh data of the element kernel are stored by colour slot (the position of

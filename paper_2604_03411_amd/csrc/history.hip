@@ -17,11 +17,25 @@
 
 namespace gedmg {
 
+// softplus(a) = max(a, 0) + log1p(e^-|a|) and the logistic s(a), with the
+// table-driven exp and log1p (tables staged in LDS by the kernel); the argument
+// of log1p is in (0, 1], where it keeps relative precision.
+__device__ __forceinline__ double softplus_tab(double a, double& s, const double* __restrict__ et,
+                                               const double* __restrict__ lt) {
+  double E, M;
+  exp_expm1_tab(-fabs(a), et, E, M);
+  const double w = 1.0 + E;
+  const double inv = rcp_d(w);
+  s = (a >= 0.0) ? inv : E * inv;
+  return fmax(a, 0.0) + log1p_tab(E, w, inv, lt);
+}
+
 // N^(q) - N^(0) and dN^/dq of the packed single-input yield network (input-
 // convex layers with a skip connection from q, softplus activations).
 template <int H, int L>
 __device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net, double yN0, double q,
-                                                  double& dN) {
+                                                  double& dN, const double* __restrict__ et,
+                                                  const double* __restrict__ lt) {
   const int stride = H * H + 2 * H;  // Wz, Wx, b of one hidden layer
   const int owz = 2 * H + (L - 1) * stride;
   double pN = 0.0, pD = 0.0;
@@ -33,7 +47,7 @@ __device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net
     for (int n = 0; n < H; ++n) {
       const double w = net[n];
       double s;
-      z[n] = softplus_d(fma(w, q, net[H + n]), s);
+      z[n] = softplus_tab(fma(w, q, net[H + n]), s, et, lt);
       zt[n] = s * w;
     }
 #pragma unroll
@@ -47,7 +61,7 @@ __device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net
     for (int n = 0; n < H; ++n) {
       const double w = net[n];
       double s;
-      z[n] = softplus_d(fma(w, q, net[H + n]), s);
+      z[n] = softplus_tab(fma(w, q, net[H + n]), s, et, lt);
       zt[n] = s * w;
     }
 #pragma unroll
@@ -66,7 +80,7 @@ __device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net
           acct = fma(Wz[n * H + m], zt[m], acct);
         }
         double s;
-        zn[n] = softplus_d(acc, s);
+        zn[n] = softplus_tab(acc, s, et, lt);
         ztn[n] = s * acct;
       }
 #pragma unroll
@@ -91,7 +105,7 @@ __device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net
         acct = fma(Wz[n * H + m], zt[m], acct);
       }
       double s;
-      const double zv = softplus_d(acc, s);
+      const double zv = softplus_tab(acc, s, et, lt);
       pN = fma(net[owz + n], zv, pN);
       pD = fma(net[owz + n], s * acct, pD);
     }
@@ -191,6 +205,11 @@ constexpr int kF32Iters = 12;
 
 template <int YH, int YL>
 __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs a) {
+  __shared__ double mt[kMathTabDoubles];  // exp table [64][2], then log table [64][4]
+  for (int i = threadIdx.x; i < kMathTabDoubles; i += blockDim.x) mt[i] = a.mtab[i];
+  __syncthreads();
+  const double* et = mt;
+  const double* lt = mt + 128;
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= a.nq) return;
   const Material M = a.m;
@@ -206,7 +225,7 @@ __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs 
   double kap = kn, dNy = 0.0;
   const double q0 = psi_e + gbe * (phi - kn) * exp_d(M.eta * fmax(kn - M.kd, 0.0));
   double d0;
-  const double h0 = yield_eval_lane<YH, YL>(a.ynet, a.yN0, q0, d0) - kn;
+  const double h0 = yield_eval_lane<YH, YL>(a.ynet, a.yN0, q0, d0, et, lt) - kn;
   dNy = d0;
   const bool yielded = h0 > 0.0;
   if (yielded) {
@@ -242,7 +261,7 @@ __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs 
       if (ks > lo && ks < hi) {
         k = ks;
         const double qk = psi_e + gbe * (phi - k) * exp_d(M.eta * fmax(k - M.kd, 0.0));
-        h = yield_eval_lane<YH, YL>(a.ynet, a.yN0, qk, dNy) - k;
+        h = yield_eval_lane<YH, YL>(a.ynet, a.yN0, qk, dNy, et, lt) - k;
         if (h > 0.0) lo = k; else hi = k;
       }
     } else {
@@ -251,7 +270,7 @@ __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs 
       // root sits just above phi: start there when the yield condition still
       // holds at phi.
       double dtop;
-      const double top = yield_eval_lane<YH, YL>(a.ynet, a.yN0, psi_e, dtop);
+      const double top = yield_eval_lane<YH, YL>(a.ynet, a.yN0, psi_e, dtop, et, lt);
       hi = fmax(fmax(kn, phi), top);
       if (phi > kn) {
         if (top - phi > 0.0) {
@@ -294,7 +313,7 @@ __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs 
       k = kn1;
       inv_f = exp_d(M.eta * fmax(k - M.kd, 0.0));
       const double qk = psi_e + gbe * (phi - k) * inv_f;
-      h = yield_eval_lane<YH, YL>(a.ynet, a.yN0, qk, dNy) - k;
+      h = yield_eval_lane<YH, YL>(a.ynet, a.yN0, qk, dNy, et, lt) - k;
       if (h > 0.0) lo = k; else hi = k;
       if (h == 0.0 || !(hi - lo > tol)) { conv = true; break; }
     }

@@ -454,7 +454,7 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
   GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[3], c->stream));
   HistArgs ha{c->dx, c->djet, c->dphiq, kappa_n, c->dynet, kappa_trial, c->dsens, c->dstatus, (long)nq,
-              c->mat, c->eref.n0, c->yref.N0, c->ylay.L, c->max_local};
+              c->mat, c->eref.n0, c->yref.N0, c->ylay.L, c->max_local, c->dmtab};
   GEDMG_HIP(c, launch_history(ha, c->ylay.H, c->stream));
   if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[4], c->stream));
   ElemArgs ea{};
