@@ -152,7 +152,7 @@ constexpr double kTabInv = 0x1.71547652b82fep+6;                                
 constexpr double kLn2Hi32 = 0x1.62e42fee00000p-1, kLn2Lo32 = 0x1.a39ef35793c76p-33;
 
 __device__ __forceinline__ void exp_expm1_tab(double t, const double* __restrict__ et, double& E, double& M) {
-  t = (t < -700.0) ? -700.0 : ((t > 700.0) ? 700.0 : t);
+  t = fma(0.0, t, fmin(fmax(t, -700.0), 700.0));  // clamp; a NaN t stays NaN
   const double kk = rint(t * kTabInv);
   const int ki = (int)kk;
   const double r = fma(-kk, kTabC2, fma(-kk, kTabC1, t));
@@ -201,7 +201,10 @@ __device__ __forceinline__ double delta_softplus_tab(double d, double a0, double
   exp_expm1_tab(fa ? d : -d, et, E, M);
   const double p = fa ? s0 : sb0, c = fa ? sb0 : s0;
   const double w = fma(p, E, c);
-  const double inv = rcp_d(w);
+  // one Newton step on the hardware estimate (11 ulp): the reciprocal only
+  // scales the logistic pair, the increment does not depend on it
+  double inv = __builtin_amdgcn_rcp(w);
+  inv = fma(inv, fma(-w, inv, 1.0), inv);
   const double sp = p * E * inv, sc = c * inv;
   s = fa ? sp : sc;
   sb = fa ? sc : sp;
