@@ -81,3 +81,37 @@ def test_full_size_cube_sampled_rows_match_oracle():
           flush=True)
     assert eR <= TOL and eK <= TOL and ek <= TOL
     ctx.close()
+
+
+def test_full_size_box_newton_path_matches_closed_form():
+    """The 32x32x8 Hex8 box (8192 elements, 39204 dofs) through its 10 affine
+    stretch load steps on the GPU Newton / Krylov path at full size.  Every
+    step's solution has a closed form that holds at any mesh size: u affine,
+    phi = kappa = N^(psi_e(F_n)) uniform, with the yield network and energy of
+    the oracle evaluated at the single deformation gradient F_n.  Tolerances as
+    in the reduced-mesh Newton tests (the uniform-damage mode is the softest)."""
+    from paper_2604_03411_amd import gedmg as G
+    case = W.make_case(2)
+    m = case.mesh
+    print(f"[full-size newton] hex8 box: {m.n_elems} elements, {m.ndof} dofs, {case.n_steps} steps", flush=True)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    model = fem.Model(case)
+    lam = case.extra["stretch"]
+    X = np.asarray(m.X)
+    for n in range(1, case.n_steps + 1):
+        u.copy_(torch.as_tensor(W.affine_stretch_guess(case, n), device=ctx.dev))
+        bd, bv = W.affine_stretch_bc(case, n)
+        rep = ctx.newton_step(u, phi, kap, bd, bv, "fp64", reaction_dofs=W.reaction_dofs(case),
+                              newton_rtol=0.0, newton_atol=1e-11, krylov_rtol=1e-13)
+        sync()
+        print(f"  step {n}: iters {rep['newton_iters']} krylov {rep['krylov_iters']} "
+              f"res {rep['res_norm'][-1]:.2e}", flush=True)
+        s = n / case.n_steps
+        ug, pg, kg = u.cpu().numpy(), phi.cpu().numpy(), kap.cpu().numpy()
+        assert np.abs(ug - s * (lam[:, None] - 1.0) * X).max() < 1e-9
+        Fn = torch.diag(torch.tensor(1.0 + s * (lam - 1.0), dtype=torch.float64))[None]
+        kref = float(model.yld(model.energy(Fn))[0])
+        assert np.abs(pg - kref).max() < 1e-6 * max(1.0, kref)
+        assert np.abs(kg - kref).max() < 1e-6 * max(1.0, kref)
+    ctx.close()
