@@ -159,3 +159,46 @@ def test_full_size_notched_path_mixed_matches_fp64(notched_fp64, precision):
     print(f"  {precision} vs fp64, max over steps: u {eu:.2e} phi {ep:.2e} reaction {er:.2e}", flush=True)
     assert eu <= 1e-8 and er <= 1e-8
     assert ep <= 1e-6
+
+
+def test_full_size_adjoint_directional_derivative():
+    """The load-path adjoint on the full 128^2 Q4 workload (20 steps,
+    checkpoints every 5, 2502 raw parameters), as the benchmark runs it:
+    reaction targets from the seeded perturbed weights, gradient at the seeded
+    weights.  Its directional derivative along a random direction (entries
+    scaled by max(1, |theta|)) against a central difference of the GPU loss
+    with step 1e-3; measured agreement about 1e-6 (the loss carries about 1e-9
+    relative noise from the converged states, truncation is O(h^2))."""
+    from paper_2604_03411_amd import gedmg as G
+    case = W.make_case(5)
+    steps = case.n_steps
+    print(f"[full-size adjoint] q4 128^2: {case.mesh.n_elems} elements, {steps} steps", flush=True)
+    ctx = G.Context.from_case(case)
+    du = np.stack([W.uniaxial_predictor(case, np.zeros_like(case.u), n) for n in range(1, steps + 1)])
+    bcs = [W.uniaxial_bc(case, n) for n in range(1, steps + 1)]
+    rd = W.reaction_dofs(case)
+    ctx.set_params(case.extra["theta_e_star"], case.extra["theta_y_star"])
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    targets = []
+    for n in range(1, steps + 1):
+        u += torch.as_tensor(du[n - 1], device=ctx.dev)
+        targets.append(ctx.newton_step(u, phi, kap, *bcs[n - 1], reaction_dofs=rd)["reaction"])
+    ctx.set_params(case.theta_e, case.theta_y)
+    path = G.LoadPath(case.u, case.phi, case.kappa, bcs, rd, targets, predictor_du=du)
+    loss, ge, gy, _ = ctx.adjoint(path, checkpoint_every=5)
+    rng = np.random.default_rng(5)
+    te, ty = case.theta_e, case.theta_y
+    n_all = te.size + ty.size
+    de = rng.standard_normal(te.size) * np.maximum(1.0, np.abs(te)) / np.sqrt(n_all)
+    dy = rng.standard_normal(ty.size) * np.maximum(1.0, np.abs(ty)) / np.sqrt(n_all)
+    gd = float(ge @ de + gy @ dy)
+    h = 1e-3
+    vals = []
+    for sgn in (1, -1):
+        ctx.set_params(te + sgn * h * de, ty + sgn * h * dy)
+        vals.append(ctx.adjoint(path, checkpoint_every=steps)[0])
+    ctx.close()
+    fd = (vals[0] - vals[1]) / (2 * h)
+    err = abs(fd - gd) / abs(gd)
+    print(f"  loss {loss:.6e}: g.d {gd:.10e} central difference {fd:.10e} rel {err:.2e}", flush=True)
+    assert err <= 1e-4
