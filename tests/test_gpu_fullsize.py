@@ -1,13 +1,19 @@
-"""Full-size parity: the 64^3 Hex8 assembly (262144 elements, 2097152 qp, the
-workload and launch configuration that bench.py times) against the oracle on
-sampled outputs.
+"""Full-size checks of the workloads at their stated sizes.
 
-The oracle cannot assemble the whole cube in seconds, so nodes are sampled
-(interior, face, edge and corner nodes) and the oracle evaluates every element
-that touches a sampled node; the rows of the sampled nodes are then complete
-and are compared with the same rows of the GPU's global R and CSR K, and the
-updated history of those elements with the GPU's kappa_trial.  Tolerance as in
-the small-mesh parity tests: 1e-12 norm-wise per output.
+- The 64^3 Hex8 assembly (262144 elements, 2097152 qp, the workload and
+  launch configuration that bench.py times) against the oracle on sampled
+  outputs.  The oracle cannot assemble the whole cube in seconds, so nodes
+  are sampled (interior, face, edge and corner nodes) and the oracle
+  evaluates every element that touches a sampled node.  The rows of the
+  sampled nodes are then complete and are compared with the same rows of the
+  GPU's global R and CSR K, and the updated history of those elements with
+  the GPU's kappa_trial.  Tolerance as in the small-mesh parity tests: 1e-12
+  norm-wise per output.
+- The 32x32x8 Hex8 box through its 10 Newton load steps, against the affine
+  closed form that holds at any mesh size.
+- The 256^2 notched Q4 plate through its 40 steps with BF16 / FP16 tangents,
+  against the FP64 path.
+- The 128^2 Q4 load-path adjoint, against a directional central difference.
 """
 import numpy as np
 import pytest
