@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs 
       const double dq = gbe * inv_f * (-1.0 + ((k > M.kd) ? M.eta * (phi - k) : 0.0));
       const double dk = div_d(-h, dNy * dq - 1.0);
       const double tol = 1e-15 * fmax(1.0, fabs(k));
-      if (fabs(dk) <= tol) {
+      if (fabs(dk) <= 1e-13 * fmax(1.0, fabs(k))) {
         k = fmin(fmax(k + dk, lo), hi);
         conv = true;
         break;
