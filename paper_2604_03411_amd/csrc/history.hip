@@ -297,6 +297,8 @@ __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs 
       const double dq = gbe * inv_f * (-1.0 + ((k > M.kd) ? M.eta * (phi - k) : 0.0));
       const double dk = div_d(-h, dNy * dq - 1.0);
       const double tol = 1e-15 * fmax(1.0, fabs(k));
+      // a correction this small leaves k + dk off by the curvature times dk^2,
+      // far below rounding, so it is accepted without a further evaluation
       if (fabs(dk) <= 1e-13 * fmax(1.0, fabs(k))) {
         k = fmin(fmax(k + dk, lo), hi);
         conv = true;
