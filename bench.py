@@ -222,8 +222,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build measures the "
-              f"single-GPU hot path; the sharded design is described, not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): it measures the "
+              f"single-GPU hot path; a sharded path is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
