@@ -138,6 +138,30 @@ class Yield:
         return self.net(q[:, None]) - self.N0
 
 
+class NeoHooke:
+    """Closed-form compressible Neo-Hooke energy of Sec. 4.1:
+    psi_NH = mu_e/2 (I1 - 3) - mu_e ln J + lambda_e/2 (ln J)^2 (mu_e, lambda_e the
+    shear and bulk moduli of the undamaged material)."""
+
+    def __init__(self, mat):
+        self.mu, self.lam = mat["mu_e"], mat["lambda_e"]
+        self.N0 = torch.zeros((), dtype=DT)
+        self.n0 = torch.zeros((), dtype=DT)
+
+    def __call__(self, F):
+        _, I1, _, _, J = invariants(F)
+        lnJ = torch.log(J)
+        return 0.5 * self.mu * (I1 - 3.0) - self.mu * lnJ + 0.5 * self.lam * lnJ * lnJ
+
+
+class IdentityYield:
+    """G(q) = q: the yield function under which Eq. potential_function becomes the
+    Ostwald loading function of Eq. ostwald_potential."""
+
+    def __call__(self, q):
+        return q * 1.0
+
+
 def f_d(kappa, mat):
     """Degradation exp(-eta_d <kappa - kappa_d>_+) (Eq. degradation_function)."""
     return torch.exp(-mat["eta_d"] * torch.clamp(kappa - mat["kappa_d"], min=0.0))
@@ -206,7 +230,7 @@ def kappa_of_z(z, kappa_star, yielded, kappa_n, energy, yld, mat, dim):
     return torch.where(yielded, k_new, kappa_n)
 
 
-def qp_response(z, kappa_n, energy, yld, mat, dim, tangent=True, create_graph=False):
+def qp_response(z, kappa_n, energy, yld, mat, dim, tangent=True, create_graph=False, update_history=True):
     """Per-qp conjugates and consistent tangent.
 
     Returns (Pz, D, kappa_{n+1}, yielded):
@@ -215,12 +239,17 @@ def qp_response(z, kappa_n, energy, yld, mat, dim, tangent=True, create_graph=Fa
            (Eqs. PK1_stress_calc, nonlocal_conjugate_calc);
       D  = dPz/dz including the history update (monolithic scheme, Sec. 3.2),
            D[b, i, j] = d Pz_i / d z_j;  None when tangent is False.
+    update_history=False holds kappa at kappa_n (the global solve of the
+    staggered scheme, Sec. 3.2): no local update, no history sensitivities.
     """
     nz = nz_of(dim)
     with torch.no_grad():
         F0, phi0, _ = fields_from_z(z.detach(), dim)
         pe0 = energy(F0)
-        kstar, yielded, _ = local_update(pe0, phi0, kappa_n.detach(), yld, mat)
+        if update_history:
+            kstar, yielded, _ = local_update(pe0, phi0, kappa_n.detach(), yld, mat)
+        else:
+            kstar, yielded = kappa_n.detach().clone(), torch.zeros_like(kappa_n, dtype=torch.bool)
     with torch.enable_grad():
         zz = z if z.requires_grad else z.detach().clone().requires_grad_(True)
         ze = zz * 1.0

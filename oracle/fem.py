@@ -121,19 +121,27 @@ def split_dofs(d, dim):
 
 
 class Model:
-    """Material + networks built from raw parameter tensors."""
+    """Material + networks built from raw parameter tensors.  A network spec with
+    no hidden layer selects the closed-form model of Sec. 4.1 instead: the
+    compressible Neo-Hooke energy, and G = identity for the yield function."""
 
     def __init__(self, case, theta_e=None, theta_y=None):
         self.mat = case.material
         te = torch.as_tensor(case.theta_e if theta_e is None else theta_e, dtype=DT)
         ty = torch.as_tensor(case.theta_y if theta_y is None else theta_y, dtype=DT)
         self.theta_e, self.theta_y = te, ty
-        self.energy = cm.Energy(te, case.energy, self.mat)
-        self.yld = cm.Yield(ty, case.yield_)
+        if case.energy.n_hidden == 0:
+            self.energy = cm.NeoHooke(self.mat)
+        else:
+            self.energy = cm.Energy(te, case.energy, self.mat)
+        if case.yield_.n_hidden == 0:
+            self.yld = cm.IdentityYield()
+        else:
+            self.yld = cm.Yield(ty, case.yield_)
 
 
 def element_response(model, mesh, d, kappa_n, elems=None, tangent=True,
-                     d_torch=None, kappa_torch=None, create_graph=False):
+                     d_torch=None, kappa_torch=None, create_graph=False, update_history=True):
     """Element residuals R_e [E, nd*nen], tangents K_e [E, nd*nen, nd*nen]
     (None if not requested) and kappa_{n+1} [E, Q] for the listed elements."""
     geo = Geometry(mesh, elems)
@@ -150,7 +158,7 @@ def element_response(model, mesh, d, kappa_n, elems=None, tangent=True,
     z = z_reference(mesh.dim, E, Q) + torch.einsum("eqzk,ek->eqz", B, de)
     Pz, D, kap, yielded = cm.qp_response(z.reshape(E * Q, -1), kn, model.energy, model.yld,
                                          model.mat, mesh.dim, tangent=tangent,
-                                         create_graph=create_graph)
+                                         create_graph=create_graph, update_history=update_history)
     nz = Pz.shape[1]
     Pz = Pz.reshape(E, Q, nz)
     Re = torch.einsum("eq,eqzk,eqz->ek", geo.Jw, B, Pz)
@@ -161,16 +169,18 @@ def element_response(model, mesh, d, kappa_n, elems=None, tangent=True,
     return geo, Re, Ke, kap.reshape(E, Q), yielded.reshape(E, Q)
 
 
-def assemble(model, mesh, d, kappa_n, tangent=True, chunk=4096):
+def assemble(model, mesh, d, kappa_n, tangent=True, chunk=4096, update_history=True):
     """Global residual R [ndof], tangent K (scipy CSR, or None) and
-    kappa_trial [n_elems, nqp] for dof vector d and history kappa_n."""
+    kappa_trial [n_elems, nqp] for dof vector d and history kappa_n
+    (update_history=False: kappa held at kappa_n, see qp_response)."""
     ndof = mesh.ndof
     R = np.zeros(ndof)
     kt = np.zeros((mesh.n_elems, mesh.nqp))
     rows, cols, vals = [], [], []
     for s in range(0, mesh.n_elems, chunk):
         el = np.arange(s, min(mesh.n_elems, s + chunk))
-        geo, Re, Ke, kap, _ = element_response(model, mesh, d, kappa_n, el, tangent)
+        geo, Re, Ke, kap, _ = element_response(model, mesh, d, kappa_n, el, tangent,
+                                               update_history=update_history)
         np.add.at(R, geo.edofs.ravel(), Re.numpy().ravel())
         kt[el] = kap.numpy()
         if tangent:

@@ -36,10 +36,19 @@ def default_atol(mesh):
     return 1e-9 * float(np.sqrt(mesh.ndof))
 
 
-def newton(model, mesh, d0, kappa_n, bc_dofs, bc_vals, rtol=1e-10, atol=None, max_iter=25):
+def newton(model, mesh, d0, kappa_n, bc_dofs, bc_vals, rtol=1e-10, atol=None, max_iter=25,
+           scheme="monolithic", rscale=1.0):
     """Solve R_f(d) = 0 for one load step.  Converged when
-    ||R_f|| <= max(rtol * max(1, ||R_f^0||), atol).  Returns (d, kappa_{n+1},
-    history, converged)."""
+    ||R_f|| <= max(rtol * max(rscale, ||R_f^0||), atol).  Returns (d, kappa_{n+1},
+    history, converged).
+
+    scheme (Sec. 3.2): "monolithic" updates the history inside every global
+    iteration (its sensitivities are part of the tangent); "staggered" solves
+    the global problem with the history held at kappa_n and updates the
+    history once, at the converged fields."""
+    if scheme not in ("monolithic", "staggered"):
+        raise ValueError(scheme)
+    upd = scheme == "monolithic"
     atol = default_atol(mesh) if atol is None else atol
     d = np.array(d0, dtype=np.float64, copy=True)
     d[bc_dofs] = bc_vals
@@ -48,12 +57,14 @@ def newton(model, mesh, d0, kappa_n, bc_dofs, bc_vals, rtol=1e-10, atol=None, ma
     hist = []
     res0 = None
     for it in range(max_iter + 1):
-        R, K, kt = fem.assemble(model, mesh, d, kappa_n)
+        R, K, kt = fem.assemble(model, mesh, d, kappa_n, update_history=upd)
         Rf = R[free]
         res = float(np.linalg.norm(Rf))
         res0 = res if res0 is None else res0
         hist.append(res)
-        if res <= max(rtol * max(1.0, res0), atol):
+        if res <= max(rtol * max(rscale, res0), atol):
+            if not upd:
+                _, _, kt = fem.assemble(model, mesh, d, kappa_n, tangent=False)
             return d, kt, hist, True
         if it == max_iter or not np.isfinite(res):
             break
@@ -67,10 +78,11 @@ def reaction(R, react_dofs):
 
 
 def load_path(case, model, steps=None, bc_fn=None, predictor_fn=None, react_dofs=None,
-              rtol=1e-10, atol=None):
+              rtol=1e-10, atol=None, scheme="monolithic", rscale=1.0):
     """Run the incremental quasi-static load path.  Returns a list of per-step
     records with the converged dofs, the history before/after and the
-    reaction force."""
+    reaction force (at the converged fields and the history the global solve
+    used: kappa_{n+1} for the monolithic scheme, kappa_n for the staggered one)."""
     import workloads as W
 
     mesh = case.mesh
@@ -85,10 +97,12 @@ def load_path(case, model, steps=None, bc_fn=None, predictor_fn=None, react_dofs
         u0 = predictor_fn(case, u, n)
         d0 = fem.dof_vector(u0, phi)
         bd, bv = bc_fn(case, n)
-        d, kt, hist, ok = newton(model, mesh, d0, kappa, bd, bv, rtol=rtol, atol=atol)
+        d, kt, hist, ok = newton(model, mesh, d0, kappa, bd, bv, rtol=rtol, atol=atol, scheme=scheme,
+                                 rscale=rscale)
         if not ok:
             raise RuntimeError(f"oracle Newton did not converge at step {n}: {hist}")
-        R, _, _ = fem.assemble(model, mesh, d, kappa, tangent=False)
+        R, _, _ = fem.assemble(model, mesh, d, kappa, tangent=False,
+                               update_history=scheme == "monolithic")
         out.append(dict(step=n, d=d.copy(), kappa_prev=kappa.copy(), kappa=kt.copy(),
                         reaction=reaction(R, react_dofs), hist=hist, bc=(bd, bv)))
         u, phi = fem.split_dofs(d, mesh.dim)

@@ -83,6 +83,8 @@ class NetSpec:
 
     @property
     def n_params(self) -> int:
+        if self.n_hidden == 0:  # closed-form model (no network)
+            return 0
         h, n = self.width, self.n_in
         return h * n + h + (self.n_hidden - 1) * (h * h + h * n + h) + h + n + 1
 
@@ -206,6 +208,21 @@ def affine_stretch_bc(case: Case, step: int):
     return np.concatenate(dofs).astype(np.int32), np.concatenate(vals)
 
 
+def boundary_field_bc(case: Case):
+    """Every dof (displacement and phi) of every boundary node prescribed to the
+    case's own nodal field: the heterogeneous-stretch cube then has a unique
+    converged interior state to compare precisions on."""
+    m = case.mesh
+    nodes = boundary_nodes(m)
+    dofs, vals = [], []
+    for c in range(m.dim):
+        dofs.append(_dof(nodes, c, m.dim))
+        vals.append(case.u[c, nodes])
+    dofs.append(_dof(nodes, m.dim, m.dim))
+    vals.append(case.phi[nodes])
+    return np.concatenate(dofs).astype(np.int32), np.concatenate(vals)
+
+
 def affine_stretch_guess(case: Case, step: int):
     """Initial guess for load step `step`: the affine field plus seeded noise."""
     m = case.mesh
@@ -232,15 +249,21 @@ def uniaxial_bc(case: Case, step: int):
     return dofs.astype(np.int32), vals
 
 
-def uniaxial_predictor(case: Case, u_prev: np.ndarray, step: int):
-    """Previous converged u plus the boundary increment spread linearly in x."""
+def uniaxial_increment(case: Case) -> np.ndarray:
+    """Predictor increment of one uniaxial load step, [dim][n_nodes]: the
+    boundary displacement increment spread linearly in x (zero on the left
+    edge, the full increment on the right edge), other components zero."""
     m = case.mesh
     x = m.X[0]
     span = x.max() - x.min()
-    du = case.extra["total_disp"] / case.n_steps
-    u = u_prev.copy()
-    u[0] = u[0] + du * (x - x.min()) / span
-    return u
+    du = np.zeros((m.dim, m.n_nodes))
+    du[0] = case.extra["total_disp"] / case.n_steps * (x - x.min()) / span
+    return du
+
+
+def uniaxial_predictor(case: Case, u_prev: np.ndarray, step: int):
+    """Previous converged u plus the boundary increment spread linearly in x."""
+    return u_prev + uniaxial_increment(case)
 
 
 def reaction_dofs(case: Case) -> np.ndarray:
@@ -331,3 +354,85 @@ def make_case(cfg: int, n: int | None = None, nz: int | None = None) -> Case:
         return Case("q4_128x128_adjoint_20_steps", mesh, mat, es, ys, te, ty, u, phi, kap, 20,
                     dict(total_disp=0.125, seed=seed, theta_e_star=pe, theta_y_star=py))
     raise ValueError(f"unknown workload {cfg}")
+
+
+# --------------------------------------------------------------------------
+# closed-form model studies (Neo-Hooke energy, G = identity yield)
+# --------------------------------------------------------------------------
+CLOSED_FORM = NetSpec(3, 0, 0, 0)     # energy: compressible Neo-Hooke (no network)
+IDENTITY_YIELD = NetSpec(1, 0, 0, 0)  # yield: G(q) = q
+
+
+def lame(E: float, nu: float):
+    """Shear and bulk-type Lame moduli (mu, lambda) of Young's modulus E and
+    Poisson ratio nu."""
+    return E / (2.0 * (1.0 + nu)), E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+
+
+def _closed_material(E, nu, eta_d, kappa_d, c_d, beta_d):
+    mu, lam = lame(E, nu)
+    return dict(mu_e=mu, lambda_e=lam, eta_d=eta_d, kappa_d=kappa_d, c_d=c_d, beta_d=beta_d, gamma_d=1.0)
+
+
+def single_element_case(eta_d: float = 10.0, kappa_d: float = 1.0, n_steps: int = 50,
+                        total_disp: float = 0.5) -> Case:
+    """One 1 x 1 x 1 mm Hex8 element of the closed-form model under uniaxial
+    tension to total_disp mm (E = 42 MPa, nu = 0.45), local model: no
+    gradient or penalty term (c_d = beta_d = 0), so q = psi_e and the nonlocal
+    field is unused (every phi dof is prescribed to 0)."""
+    mesh = hex8_grid(1, 1, 1)
+    mat = _closed_material(42.0, 0.45, eta_d, kappa_d, 0.0, 0.0)
+    u, phi, kap = _uniaxial_fields(mesh)
+    return Case(f"hex8_single_element_eta{eta_d:g}_kd{kappa_d:g}", mesh, mat, CLOSED_FORM, IDENTITY_YIELD,
+                np.zeros(0), np.zeros(0), u, phi, kap, n_steps, dict(total_disp=total_disp, local=True))
+
+
+def uniform_plate_case(mesh_kind: str = "coarse", nonlocal_: bool = True, n_steps: int = 1000,
+                       total_disp: float = 1.0, seed: int = 7) -> Case:
+    """The 10 x 10 x 1 mm plate of the uniform-deformation study with the
+    closed-form model (E = 210 MPa, nu = 0.3, eta_d = 0.002, kappa_d = 0.1,
+    c_d = 1, beta_d = 1000), one Hex8 element through the thickness.
+    mesh_kind: "coarse" (10 x 10), "refined" (20 x 20) or "nonuniform" (10 x 10
+    with the interior node columns and rows moved by a seeded +-30 % of the
+    spacing).  nonlocal_=False gives the local model (c_d = beta_d = 0, every
+    phi dof prescribed to 0)."""
+    n = {"coarse": 10, "refined": 20, "nonuniform": 10}[mesh_kind]
+    mesh = hex8_grid(n, n, 1, 10.0, 10.0, 1.0)
+    if mesh_kind == "nonuniform":
+        rng = np.random.default_rng(seed)
+        h = 10.0 / n
+        sx = np.concatenate([[0.0], np.arange(1, n) * h + rng.uniform(-0.3, 0.3, n - 1) * h, [10.0]])
+        sy = np.concatenate([[0.0], np.arange(1, n) * h + rng.uniform(-0.3, 0.3, n - 1) * h, [10.0]])
+        i = np.rint(mesh.X[0] / h).astype(int)
+        j = np.rint(mesh.X[1] / h).astype(int)
+        mesh.X[0] = sx[i]
+        mesh.X[1] = sy[j]
+    cd, bd = (1.0, 1000.0) if nonlocal_ else (0.0, 0.0)
+    mat = _closed_material(210.0, 0.3, 0.002, 0.1, cd, bd)
+    u, phi, kap = _uniaxial_fields(mesh)
+    return Case(f"hex8_plate_{mesh_kind}_{'nonlocal' if nonlocal_ else 'local'}", mesh, mat, CLOSED_FORM,
+                IDENTITY_YIELD, np.zeros(0), np.zeros(0), u, phi, kap, n_steps,
+                dict(total_disp=total_disp, local=not nonlocal_))
+
+
+def symmetric_tension_bc(case: Case, step: int):
+    """Uniaxial tension of a box: u_x = 0 on the face x = min, u_y = 0 on
+    y = min, u_z = 0 on z = min (symmetry planes), u_x = total * step / n_steps
+    on x = max; with case.extra["local"] every phi dof is prescribed to 0."""
+    m = case.mesh
+    X = m.X
+    lo = X.min(axis=1)
+    hi_x = X[0].max()
+    dofs, vals = [], []
+    for c in range(m.dim):
+        on = np.nonzero(np.abs(X[c] - lo[c]) < 1e-12)[0]
+        dofs.append(_dof(on, c, m.dim))
+        vals.append(np.zeros(on.size))
+    right = np.nonzero(np.abs(X[0] - hi_x) < 1e-12)[0]
+    dofs.append(_dof(right, 0, m.dim))
+    vals.append(np.full(right.size, case.extra["total_disp"] * step / case.n_steps))
+    if case.extra.get("local"):
+        allnodes = np.arange(m.n_nodes)
+        dofs.append(_dof(allnodes, m.dim, m.dim))
+        vals.append(np.zeros(m.n_nodes))
+    return np.concatenate(dofs).astype(np.int32), np.concatenate(vals)
