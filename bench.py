@@ -40,22 +40,31 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
 PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 / FP16 matrix
 PEAK_HBM_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2604_03411_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_energy_jet_fp64_hex8_64cube.txt")
-JET_SOURCES = [os.path.join(ROOT, "paper_2604_03411_amd", "csrc", n)
-               for n in ("icnn_jet.hip", "device_common.h")]
+JET_SOURCES = [os.path.join(CSRC, n) for n in ("icnn_jet.hip", "device_common.h")]
+ELEM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_element_hex8_64cube.txt")
+ELEM_SOURCES = [os.path.join(CSRC, n) for n in ("element.hip", "device_common.h")]
+MFMA_FILE = os.path.join(ROOT, "profiles", "mfma_busy_energy_jet_fp64_hex8_64cube.txt")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def jet_flops_per_qp(width, n_hidden, with_hessian=True):
-    """Matrix-core flops of the energy-network jet per quadrature point: each
-    hidden->hidden layer multiplies 4 forward columns (activation increment and
-    three input tangents) and, for the Hessian, 1 adjoint column by the
-    width x width weights: 2 * width^2 flops per column."""
-    cols = 5 if with_hessian else 4
-    return (n_hidden - 1) * cols * 2 * width * width
+def jet_flops_per_qp(width, n_hidden):
+    """Algorithmic matrix work of the energy-network jet per quadrature point:
+    value, gradient (3) and Hessian (6) of the network with respect to its 3
+    inputs are 10 columns per point, each multiplied by every width x width
+    hidden->hidden weight matrix: (n_hidden - 1) * 10 * 2 * width^2 flops."""
+    return (n_hidden - 1) * 10 * 2 * width * width
+
+
+def jet_issued_flops_per_qp(width, n_hidden):
+    """Matrix flops the FP64 jet kernel actually issues: 4 forward columns
+    (activation increment, 3 input tangents) and 1 adjoint column per layer;
+    the Hessian comes from the adjoint column and the tangents."""
+    return (n_hidden - 1) * 5 * 2 * width * width
 
 
 def time_assembly(ctx, fields, out, precision, steps, warmup, torch):
@@ -96,12 +105,11 @@ def mixed_newton_error(G, W, torch, precision):
         ctx = G.Context.from_case(case)
         u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
         iters = 0
+        du = W.uniaxial_increment(case)
         for n in range(1, 5):
-            u0 = W.uniaxial_predictor(case, u.cpu().numpy(), n)
-            u.copy_(torch.as_tensor(u0, device=ctx.dev))
             bd, bv = W.uniaxial_bc(case, n)
             rep = ctx.newton_step(u, phi, kap, bd, bv, prec, reaction_dofs=W.reaction_dofs(case),
-                                  newton_rtol=0.0, newton_atol=1e-11, krylov_rtol=1e-13)
+                                  predictor_du=du, newton_rtol=0.0, newton_atol=1e-11, krylov_rtol=1e-13)
             iters += rep["newton_iters"]
         torch.cuda.synchronize()
         out[prec] = (u.clone(), phi.clone(), rep["reaction"], iters)
@@ -112,8 +120,36 @@ def mixed_newton_error(G, W, torch, precision):
                 path="notched Q4 32x32, 4 tension steps, ||R_f|| <= 1e-11")
 
 
-def bench_mixed(G, W, torch, ctx, fields, out, ref, steps, warmup, nq):
+def cube_converged(G, W, torch, ctx, case, precision):
+    """Converged state of the 64^3 heterogeneous-stretch cube with every
+    boundary node (u and phi) prescribed to the seeded field and the interior
+    solved by Newton (FP64 residual, tangent in `precision`): the converged-
+    displacement recipe of the mixed-precision error report.  Returns u, phi,
+    iterations and the wall time per Newton iteration."""
+    import math
+
+    bd, bv = W.boundary_field_bc(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    atol = 1e-9 * math.sqrt(case.mesh.ndof)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = ctx.newton_step(u, phi, kap, bd, bv, precision, newton_rtol=1e-10, newton_atol=atol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its = max(rep["newton_iters"], 1)
+    return u, phi, dict(newton_iters=rep["newton_iters"], krylov_iters=rep["krylov_iters"],
+                        s_total=dt, ms_per_newton_iter=1e3 * dt / its, residual=rep["res_norm"][-1])
+
+
+def bench_mixed(G, W, torch, ctx, fields, out, ref, steps, warmup, nq, case=None, cube_newton=True):
     res = {}
+    cube_ref = None
+    if cube_newton:
+        log("64^3 cube, boundary on the seeded field: FP64 Newton solve")
+        cube_ref = cube_converged(G, W, torch, ctx, case, "fp64")
+        log(f"  fp64: {cube_ref[2]['newton_iters']} Newton / {cube_ref[2]['krylov_iters']} Krylov iterations, "
+            f"{cube_ref[2]['ms_per_newton_iter']:.1f} ms per Newton iteration")
+        res["fp64_cube_newton"] = cube_ref[2]
     for prec in ("bf16", "fp16"):
         try:
             ms, prof = time_assembly(ctx, fields, out, prec, steps, warmup, torch)
@@ -125,6 +161,15 @@ def bench_mixed(G, W, torch, ctx, fields, out, ref, steps, warmup, nq):
         log(f"{prec}: {ms / steps:.3f} ms/step, residual err {errs['residual']:.2e} "
             f"tangent err {errs['tangent']:.2e}; converged-displacement check")
         errs.update(mixed_newton_error(G, W, torch, prec))
+        if cube_ref is not None:
+            u1, p1, info = cube_converged(G, W, torch, ctx, case, prec)
+            info.update(displacement=rel_err(u1, cube_ref[0]), phi=rel_err(p1, cube_ref[1]),
+                        recipe="64^3 cube, every boundary node (u, phi) on the seeded field, interior solved; "
+                               "relative error against the FP64 GPU solve (both to ||R_f|| <= "
+                               "max(1e-10 ||R_f^0||, 1e-9 sqrt(ndof)))")
+            errs["converged_cube"] = info
+            log(f"  {prec} cube: u err {info['displacement']:.2e}, {info['newton_iters']} Newton iterations, "
+                f"{info['ms_per_newton_iter']:.1f} ms each")
         res[prec] = dict(value=nq / (ms / steps * 1e-3), unit="qp/s", ms_per_step=ms / steps,
                          jet_ms=per_call(prof, "jets"), history_ms=per_call(prof, "history"),
                          element_ms=per_call(prof, "elements"),
@@ -140,15 +185,15 @@ def bench_adjoint(G, W, torch, checkpoint_every=5):
     case = W.make_case(5)
     steps = case.n_steps
     ctx = G.Context.from_case(case)
-    du = np.stack([W.uniaxial_predictor(case, np.zeros_like(case.u), n) for n in range(1, steps + 1)])
+    du = np.stack([W.uniaxial_increment(case)] * steps)
     bcs = [W.uniaxial_bc(case, n) for n in range(1, steps + 1)]
     rd = W.reaction_dofs(case)
     ctx.set_params(case.extra["theta_e_star"], case.extra["theta_y_star"])
     u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
     targets = []
     for n in range(1, steps + 1):
-        u += torch.as_tensor(du[n - 1], device=ctx.dev)
-        targets.append(ctx.newton_step(u, phi, kap, *bcs[n - 1], reaction_dofs=rd)["reaction"])
+        targets.append(ctx.newton_step(u, phi, kap, *bcs[n - 1], reaction_dofs=rd,
+                                       predictor_du=du[n - 1])["reaction"])
     ctx.set_params(case.theta_e, case.theta_y)
     path = G.LoadPath(case.u, case.phi, case.kappa, bcs, rd, targets, predictor_du=du)
     torch.cuda.synchronize()
@@ -162,8 +207,23 @@ def bench_adjoint(G, W, torch, checkpoint_every=5):
                 newton_iters=rep["newton_iters_total"], krylov_iters=rep["krylov_iters_total"])
 
 
-def cpu_baseline(case, n_elems):
-    """The oracle, as it stands, on the first n_elems elements of the workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, n_elems_all, n_elems_one, runs=3):
+    """The oracle, as it stands, on the first elements of the workload: the
+    median of `runs` timings on all of the host threads torch uses and on one
+    thread."""
+    import statistics
+
     import torch
 
     import workloads as W
@@ -171,33 +231,64 @@ def cpu_baseline(case, n_elems):
 
     model = fem.Model(case)
     d = fem.dof_vector(case.u, case.phi)
-    sub = W.Mesh(case.mesh.dim, case.mesh.X, case.mesh.conn[:n_elems])
-    t0 = time.perf_counter()
-    fem.assemble(model, sub, d, case.kappa[:n_elems])
-    dt = time.perf_counter() - t0
-    nq = n_elems * case.mesh.nqp
-    return dict(value=nq / dt, unit="qp/s", cores=torch.get_num_threads(), kind="oracle",
-                sample=f"FP64 residual+tangent assembly of the first {n_elems} elements "
-                       f"({nq} qp) of the 64^3 Hex8 workload, {dt:.1f} s")
+    threads_all = torch.get_num_threads()
+
+    def rate(n_elems, threads):
+        torch.set_num_threads(threads)
+        sub = W.Mesh(case.mesh.dim, case.mesh.X, case.mesh.conn[:n_elems])
+        ts = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            fem.assemble(model, sub, d, case.kappa[:n_elems])
+            ts.append(time.perf_counter() - t0)
+        return n_elems * case.mesh.nqp / statistics.median(ts), ts
+
+    v_all, t_all = rate(n_elems_all, threads_all)
+    v_one, t_one = rate(n_elems_one, 1)
+    torch.set_num_threads(threads_all)
+    return dict(value=v_all, unit="qp/s", cores=threads_all, kind="oracle",
+                sample=f"FP64 residual+tangent assembly of the first {n_elems_all} elements "
+                       f"({n_elems_all * case.mesh.nqp} qp) of the 64^3 Hex8 workload on {threads_all} threads, "
+                       f"median of {runs} ({', '.join(f'{t:.1f}' for t in t_all)} s); one thread: the first "
+                       f"{n_elems_one} elements, median of {runs} ({', '.join(f'{t:.1f}' for t in t_one)} s)",
+                single_thread=dict(value=v_one, unit="qp/s", cores=1),
+                nproc=os.cpu_count(), cpu_model=cpu_model())
 
 
-def jet_traffic(launch_bytes_alg):
-    """HBM bytes per jet launch from the committed rocprofv3 counter summary,
-    if it was taken on the current jet sources (kernel and its device math);
-    else None."""
+def profile_record(path, sources, key="jet_source_sha256"):
+    """The JSON record of a committed rocprofv3 counter summary, if it was
+    taken on the current sources of the kernel (its SHA-256 over `sources`
+    matches); else None (counters of a changed kernel are not reported)."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.loads([ln for ln in f if ln.startswith("{")][-1])
         h = hashlib.sha256()
-        for path in JET_SOURCES:
-            with open(path, "rb") as f:
+        for p in sources:
+            with open(p, "rb") as f:
                 h.update(f.read())
         digest = h.hexdigest()
     except (OSError, ValueError, IndexError):
         return None
-    if rec.get("jet_source_sha256") != digest:
+    if rec.get(key) != digest:
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def jet_traffic():
+    """HBM bytes per jet launch from the committed counter summary, or None."""
+    rec = profile_record(TRAFFIC_FILE, JET_SOURCES)
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def element_alg_bytes(case, nnz):
+    """Algorithmic HBM bytes of the element phase of one assembly: the CSR values
+    and the residual written once; nodal u, phi and coordinates and the
+    connectivity read once; per point the jet row (80 B), the updated history
+    (8 B) and its two sensitivities (16 B) read once."""
+    m = case.mesh
+    nq = m.n_elems * m.nqp
+    return (8 * nnz + 8 * m.ndof + 8 * (2 * m.dim + 1) * m.n_nodes + 4 * m.n_elems * m.nen
+            + nq * (80 + 8 + 16))
 
 
 def copy_probe(torch, mib=1024, reps=3):
@@ -216,10 +307,17 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-elems", type=int, default=49152)
+    ap.add_argument("--cpu-sample-elems", type=int, default=8192,
+                    help="elements of the oracle sample timed on all host threads")
+    ap.add_argument("--cpu-sample-elems-1t", type=int, default=1024,
+                    help="elements of the oracle sample timed on one thread")
+    ap.add_argument("--no-cube-newton", action="store_true",
+                    help="skip the converged-displacement solves of the 64^3 cube")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="run the FP64 matrix-core calibration probe first (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): it measures the "
@@ -234,6 +332,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(torch)
+    if args.mfma_probe:
+        n = G.probe_mfma(4 * 256, 4000)
+        log(f"mfma probe: {n} FP64 16x16x4 products ({n * 2048 / 1e9:.1f} GFLOP)")
     case = W.make_case(4)
     mesh = case.mesh
     nq = mesh.n_elems * mesh.nqp
@@ -252,17 +353,29 @@ def main():
     fill_ms, in_ms, hist_ms = per_call(prof, "fills"), per_call(prof, "inputs"), per_call(prof, "history")
     flops = jet_flops_per_qp(H, L) * nq
     jet_tf = flops / (jet_ms * 1e-3) / 1e12
-    traffic = jet_traffic(nq * (3 + 10) * 8)
+    issued_tf = jet_issued_flops_per_qp(H, L) * nq / (jet_ms * 1e-3) / 1e12
+    mfma = profile_record(MFMA_FILE, JET_SOURCES)
     roofline = dict(bound="mfma", achieved=round(jet_tf, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                    frac=round(jet_tf / PEAK_FP64_TFLOPS, 4), traffic=traffic, kernel="jet_f64_kernel",
-                    flops_per_qp=jet_flops_per_qp(H, L), qp_per_launch=nq, ms_per_launch=round(jet_ms, 4))
+                    frac=round(jet_tf / PEAK_FP64_TFLOPS, 4), traffic=jet_traffic(), kernel="jet_f64_kernel",
+                    flops_per_qp=jet_flops_per_qp(H, L), qp_per_launch=nq, ms_per_launch=round(jet_ms, 4),
+                    issued_flops_per_qp=jet_issued_flops_per_qp(H, L),
+                    issued_frac=round(issued_tf / PEAK_FP64_TFLOPS, 4),
+                    mfma_busy_frac=None if mfma is None else mfma.get("mfma_busy_frac"))
+    eb = element_alg_bytes(case, ctx.nnz)
+    erec = profile_record(ELEM_TRAFFIC_FILE, ELEM_SOURCES, key="source_sha256")
+    element_roofline = dict(bound="hbm", achieved=round(eb / (elem_ms * 1e-3) / 1e9, 1), peak=PEAK_HBM_GBS,
+                            unit="GB/s", frac=round(eb / (elem_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                            traffic=None if erec is None else erec.get("bytes_per_assembly"),
+                            kernel="element_kernel (all colours of one assembly)", algorithmic_bytes=eb,
+                            ms_per_assembly=round(elem_ms, 4))
     log(f"{ms_step:.3f} ms/step; phases ms: inputs {in_ms:.3f} jets {jet_ms:.3f} history {hist_ms:.3f} "
         f"elements {elem_ms:.3f} fills {fill_ms:.3f}")
 
     extra = {}
     if not args.no_mixed:
         ref = (out[0].clone(), out[1].clone())
-        extra["mixed"] = bench_mixed(G, W, torch, ctx, fields, out, ref, args.steps, args.warmup, nq)
+        extra["mixed"] = bench_mixed(G, W, torch, ctx, fields, out, ref, args.steps, args.warmup, nq, case,
+                                     not args.no_cube_newton)
         del ref
     ctx.close()
     del out, fields
@@ -274,8 +387,9 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"timing the oracle on {args.cpu_sample_elems} elements")
-        cpu = cpu_baseline(case, args.cpu_sample_elems)
+        log(f"timing the oracle on {args.cpu_sample_elems} elements (all threads) and "
+            f"{args.cpu_sample_elems_1t} elements (one thread)")
+        cpu = cpu_baseline(case, args.cpu_sample_elems, args.cpu_sample_elems_1t)
 
     line = dict(
         metric="qp residual+tangent evals/sec", value=value, unit="qp/s", n_gpus=1,
@@ -286,7 +400,7 @@ def main():
                     precision="fp64"),
         phases_ms=dict(inputs=in_ms, jets=jet_ms, history=hist_ms, elements=elem_ms, fills=fill_ms,
                        dominant="energy_jet" if jet_ms >= elem_ms else "element"),
-        roofline=roofline, cpu_baseline=cpu, **extra)
+        roofline=roofline, element_roofline=element_roofline, cpu_baseline=cpu, **extra)
     print(json.dumps(line), flush=True)
 
 

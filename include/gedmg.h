@@ -88,9 +88,15 @@ typedef struct {
 typedef struct {
   int32_t n_in;           /* 3 for the energy network, 1 for the yield network */
   int32_t width;          /* hidden width: energy 16, 32 or 64; yield 16 or 32 */
-  int32_t n_hidden;       /* number of hidden layers (1..3) */
+  int32_t n_hidden;       /* number of hidden layers (1..3), or 0 for the closed-form model of
+                             Sec. 4.1: energy psi_e = compressible Neo-Hooke
+                             mu_e/2 (I1 - 3) - mu_e ln J + lambda_e/2 (ln J)^2 (width, mask and
+                             theta ignored); yield G(q) = q, which makes the yield condition the
+                             loading function of Eq. ostwald_potential.  Either network may be
+                             closed-form independently. */
   int32_t monotone_mask;  /* energy: 3 (I1G, I2G); yield: 1 */
-  const double* theta;    /* host, raw parameters in the order described above */
+  const double* theta;    /* host, raw parameters in the order described above (NULL allowed
+                             when n_hidden == 0) */
 } gedmg_icnn;
 
 typedef struct {
@@ -103,7 +109,7 @@ typedef struct {
   int32_t max_newton;     /* global Newton iterations (default 25) */
   int32_t max_krylov;     /* Krylov iterations per linear solve (default 20000) */
   int32_t max_local;      /* history-update iterations (default 100, as in the paper's notched plate) */
-  double newton_rtol;     /* ||R_f|| <= max(newton_rtol * max(1, ||R_f^0||), newton_atol) */
+  double newton_rtol;     /* ||R_f|| <= max(newton_rtol * max(newton_rscale, ||R_f^0||), newton_atol) */
   double newton_atol;
   double krylov_rtol;     /* relative residual of each linear solve (default 1e-12) */
   int32_t krylov_forcing; /* 1 (default): inexact Newton, iteration k solves to the relative residual
@@ -111,7 +117,28 @@ typedef struct {
                              not pay for accuracy the Newton residual cannot use; 0: every solve to
                              krylov_rtol.  The Newton test on the FP64 residual decides convergence
                              either way. */
+  /* Mixed precision (precision != GEDMG_FP64): each iteration solves with the
+   * low-precision tangent against the FP64 residual, i.e. one pass of iterative
+   * refinement.  refine_max extra iterations are allowed on top of max_newton
+   * (default 10), and each solve stops at the relative residual
+   * max(refine_rtol, the FP64 rule above): the tangent itself carries relative
+   * errors of about 1e-5 (FP16) to 1e-4 (BF16), so accuracy below that is not
+   * used by the refinement (default 1e-8; 0 keeps the FP64 rule). */
+  int32_t refine_max;
+  double refine_rtol;
+  /* Solution scheme of the history variable (Sec. 3.2): GEDMG_MONOLITHIC (default)
+   * updates kappa inside every global Newton iteration with its sensitivities in
+   * the tangent; GEDMG_STAGGERED solves the global problem with kappa held at
+   * kappa_n (no history sensitivities) and updates kappa once at the converged
+   * fields, so the history lags the fields by one load step. */
+  int32_t scheme;
+  /* Residual scale of the relative Newton test (default 1, so residuals below 1
+   * are tested absolutely); 0 makes the test purely relative to ||R_f^0||, for
+   * states whose whole residual is scaled by a tiny degradation f_d. */
+  double newton_rscale;
 } gedmg_solver_opts;
+
+enum { GEDMG_MONOLITHIC = 0, GEDMG_STAGGERED = 1 };
 
 typedef struct {
   int32_t newton_iters;       /* assemblies - 1 */
@@ -133,11 +160,20 @@ typedef struct {
 /* Message for the last failure on this context (never NULL). */
 const char* gedmg_last_error(const gedmg_ctx* ctx);
 
-/* Build a context: copies the mesh, builds the CSR pattern of the (dim+1)^2
- * node-pair blocks, the element colouring and the element -> CSR offset map,
- * and uploads the effective network weights.  hip_stream may be NULL (the
- * null stream).  Returns GEDMG_E_SHAPE for widths other than 16/32/64,
- * energy n_in != 3, yield n_in != 1 or n_hidden outside 1..3. */
+/* Build a context for one mesh, material and pair of networks: the element
+ * data the residual kernel consumes (Table 1: nodal coordinates from which the
+ * shape-function gradients and quadrature measures follow, connectivity for
+ * the nodal u and phi values) and the ICNN parameters of Eqs. dd_0 and Gq_NN.
+ * Copies the mesh, builds the CSR pattern of the (dim+1)^2 node-pair blocks,
+ * the element colouring and the element -> CSR offset map, and uploads the
+ * effective network weights.  All pointers in the descriptors are HOST
+ * pointers, read during the call only.  hip_stream may be NULL (the null
+ * stream).  On failure *ctx still receives a context (when it could be
+ * allocated) whose gedmg_last_error() explains the failure; destroy it.
+ * Returns GEDMG_E_ARG for null or empty meshes and connectivity indices out of
+ * range, GEDMG_E_SHAPE for widths other than 16/32/64, energy n_in != 3, yield
+ * n_in != 1, n_hidden outside 0..3 or more than 2^31 CSR entries,
+ * GEDMG_E_NOMEM / GEDMG_E_HIP for device failures. */
 int gedmg_create(gedmg_ctx** ctx, const gedmg_mesh* mesh, const gedmg_material* mat,
                  const gedmg_icnn* energy, const gedmg_icnn* yield, void* hip_stream);
 int gedmg_destroy(gedmg_ctx* ctx);
@@ -183,21 +219,49 @@ int gedmg_energy_jet(gedmg_ctx* ctx, const double* x, int64_t n, int precision, 
 int gedmg_profile(gedmg_ctx* ctx, int enable);
 int gedmg_profile_read(gedmg_ctx* ctx, double* out_ms, int32_t* n_calls);
 
+/* Counter calibration (for profiling only): launches `blocks` workgroups of
+ * 256 threads (4 waves) on hip_stream, each wave issuing 4 x iters FP64
+ * 16x16x4 matrix products (2048 flop each) and nothing else, so an MFMA-busy
+ * counter reading can be related to a known number of products.  sink: device
+ * [blocks * 256] doubles that receive the sums (keeps the products live).
+ * Returns GEDMG_E_ARG for null sink or non-positive sizes. */
+int gedmg_probe_mfma(double* sink, int32_t blocks, int32_t iters, void* hip_stream);
+
 /* Synchronise the stream and return the sticky device status of the last
  * assemblies (GEDMG_OK, GEDMG_E_LOCAL_NOCONV or GEDMG_E_JNONPOS), then clear it. */
 int gedmg_status(gedmg_ctx* ctx);
 
-/* One load step of the monolithic scheme: sets the prescribed dofs, then
- * Newton on the free dofs, starting from the (u, phi) passed in (the caller's
- * predictor), with a Jacobi-preconditioned Krylov solve of K_ff d = -R_f per
- * iteration (CG; BiCGStab when CG breaks down on a non-symmetric or
- * indefinite tangent).  precision != GEDMG_FP64 uses the mixed-precision
- * tangent with the FP64 residual (iterative refinement).  On success u, phi
- * hold the converged state and kappa the committed history kappa_{n+1}; on
- * failure all three are restored.  reaction_dofs (device, may be NULL when
- * n_reaction == 0) selects the rows summed into report->reaction. */
+/* One load step of incremental quasi-static loading (Sec. 3.2; the step starts
+ * from the last converged solution), with the monolithic scheme by default (the
+ * history update of Eq. dd_7 runs inside every global Newton iteration and its
+ * sensitivities enter the tangent) or the staggered one (opts->scheme).  The call
+ *   1. adds the predictor increment predictor_du (device [dim][n_nodes], may be
+ *      NULL for none) to u: the caller's extrapolation of the last converged
+ *      displacement, e.g. the boundary increment spread over the body;
+ *   2. sets the prescribed dofs bc (device dof / value arrays);
+ *   3. runs Newton on the free dofs, with a preconditioned Krylov solve of
+ *      K_ff d = -R_f per iteration (CG with Jacobi plus a coarse correction on
+ *      the uniform damage field; BiCGStab with Jacobi when CG meets
+ *      non-positive curvature on a non-symmetric or indefinite tangent), until
+ *      ||R_f|| <= max(newton_rtol max(newton_rscale, ||R_f^0||), newton_atol);
+ *   4. commits kappa_{n+1} (staggered: the local update of Eq. dd_7 at the
+ *      converged fields, computed once after the global solve with kappa_n).
+ * precision != GEDMG_FP64 uses the mixed-precision tangent with the FP64
+ * residual (iterative refinement, see refine_max / refine_rtol).  u, phi:
+ * device [dim][n_nodes], [n_nodes], in: the last converged state, out: the
+ * converged state; kappa: device [n_elems][nqp], in kappa_n, out kappa_{n+1}.
+ * On failure all three are restored to their input values (before the
+ * predictor).  opts may be NULL (defaults).  reaction_dofs (device, distinct,
+ * in range; may be NULL when n_reaction == 0) selects the rows of the converged
+ * residual summed into report->reaction (staggered: the residual of the global
+ * solve, with the history at kappa_n).  report is a host struct, may be NULL.
+ * Synchronises the stream.  Allocates its Krylov workspace on the first call
+ * for a context (freed by gedmg_destroy).  Errors: GEDMG_E_ARG (null or
+ * inconsistent arguments, dofs out of range), GEDMG_E_NONFINITE,
+ * GEDMG_E_LOCAL_NOCONV, GEDMG_E_JNONPOS, GEDMG_E_LINSOLVE,
+ * GEDMG_E_NEWTON_NOCONV, GEDMG_E_NOMEM, GEDMG_E_HIP. */
 int gedmg_newton_step(gedmg_ctx* ctx, const gedmg_dirichlet* bc, const gedmg_solver_opts* opts,
-                      int precision, double* u, double* phi, double* kappa,
+                      int precision, const double* predictor_du, double* u, double* phi, double* kappa,
                       const int32_t* reaction_dofs, int32_t n_reaction,
                       gedmg_newton_report* report);
 

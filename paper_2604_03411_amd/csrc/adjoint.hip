@@ -557,11 +557,6 @@ __global__ void transpose_values_kernel(const double* K, const int32_t* permT, d
   if (i < nnz) KT[i] = K[permT[i]];
 }
 
-__global__ void axpy_kernel(double* y, const double* x, long n) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] += x[i];
-}
-
 // e = indicator of the reaction dofs (distinct, in range: checked on the host).
 __global__ void indicator_kernel(double* e, const int32_t* rd, int nr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -648,11 +643,15 @@ extern "C" int gedmg_adjoint(gedmg_ctx* c, int32_t n_steps, const gedmg_dirichle
     c->err = "null or inconsistent adjoint argument";
     return GEDMG_E_ARG;
   }
+  if (c->closed_energy || c->closed_yield) {
+    c->err = "the adjoint differentiates network parameters; the closed-form model has none";
+    return GEDMG_E_SHAPE;
+  }
   if (c->ylay.H > kMaxYieldWidth) {
     c->err = "yield-network width above 32 is not supported by the adjoint";
     return GEDMG_E_SHAPE;
   }
-  gedmg_solver_opts o{25, 20000, 100, 1e-10, 0.0, 1e-12, 1};
+  gedmg_solver_opts o = default_solver_opts();
   if (opts_in) o = *opts_in;
   gedmg_adjoint_report local{};
   gedmg_adjoint_report& R = rep ? *rep : local;
@@ -723,12 +722,10 @@ extern "C" int gedmg_adjoint(gedmg_ctx* c, int32_t n_steps, const gedmg_dirichle
   int newton_its = 0, krylov_its = 0;
   // one converged load step from the current (u, phi, kappa)
   auto step = [&](int n) -> int {
-    if (predictor_du)
-      hipLaunchKernelGGL(axpy_kernel, grid1(nu), dim3(256), 0, c->stream, u, predictor_du + (long)(n - 1) * nu,
-                         nu);
     gedmg_newton_report nr{};
-    const int rc = gedmg_newton_step(c, &bc_per_step[n - 1], &o, GEDMG_FP64, u, phi, kappa, reaction_dofs,
-                                     n_reaction, &nr);
+    const int rc = gedmg_newton_step(c, &bc_per_step[n - 1], &o, GEDMG_FP64,
+                                     predictor_du ? predictor_du + (long)(n - 1) * nu : nullptr, u, phi, kappa,
+                                     reaction_dofs, n_reaction, &nr);
     newton_its += nr.newton_iters;
     krylov_its += nr.krylov_iters_total;
     if (rc) return rc;

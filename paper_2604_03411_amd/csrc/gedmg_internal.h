@@ -78,6 +78,7 @@ struct JetArgs {
   int L;
   int with_hessian;
   const double* mtab;    // [kMathTabDoubles] exp / log tables (FP64 kernel)
+  double cf_mu, cf_lam;  // closed-form model (L == 0): Neo-Hooke moduli
 };
 
 struct KinArgs {
@@ -105,8 +106,9 @@ struct HistArgs {
   Material m;
   double n0;             // energy network dN/dx3 at 0
   double yN0;            // yield network N(0)
-  int yL;
+  int yL;                // hidden layers of the yield network; 0: G = identity (closed-form model)
   int max_local;
+  int frozen;            // 1: keep kappa_n and report zero sensitivities (staggered scheme)
   const double* mtab;    // exp / log tables of the table-driven FP64 functions (kMathTabDoubles)
 };
 
@@ -141,9 +143,32 @@ void build_math_tables(std::vector<double>& t);
 // Kernel launchers (defined in the .hip translation units).
 hipError_t launch_qp_inputs(int dim, const KinArgs& a, hipStream_t s);
 hipError_t launch_energy_jet(int precision, int H, const JetArgs& a, hipStream_t s, int num_cu);
+hipError_t launch_closed_form_jet(const JetArgs& a, hipStream_t s);
 hipError_t launch_history(const HistArgs& a, int yH, hipStream_t s);
 hipError_t launch_element(int dim, bool tangent, const ElemArgs& a, hipStream_t s);
 void release_newton_work(gedmg_ctx* c);
+
+// Per-point scratch of one assembly: network inputs x [nq][3], jets [nq][10],
+// phi at the points [nq] and the history sensitivities [nq][2].
+struct AssembleScratch {
+  double* x;
+  double* jet;
+  double* phiq;
+  double* sens;
+};
+
+// Material seen by the history and element kernels (unit energy scale and no
+// volumetric term for the closed-form energy, whose jet is the whole psi_e).
+Material element_material(const gedmg_ctx* c);
+
+// One assembly (gedmg_assemble) with the given scratch.  fill_kernel: clear R
+// with a kernel instead of hipMemsetAsync and record no profiling events (the
+// form that a caller may capture in a graph).
+int assemble_impl(gedmg_ctx* c, const double* u, const double* phi, const double* kappa_n, int precision,
+                  double* R, double* K_vals, double* kappa_trial, const AssembleScratch& sc, bool fill_kernel);
+
+// Defaults of gedmg_solver_opts (used when a caller passes NULL).
+gedmg_solver_opts default_solver_opts();
 
 // Sparse helpers of the Newton driver, reused by the adjoint.
 // y = K x over the context's CSR pattern.
@@ -190,6 +215,9 @@ struct gedmg_ctx {
   double* dsens = nullptr;             // [nq][2]
   int* dstatus = nullptr;
   int max_local = 100;                 // history-update iteration limit
+  int frozen_history = 0;              // staggered scheme: assemblies keep kappa_n (set by newton_step)
+  bool closed_energy = false;          // energy: compressible Neo-Hooke (Sec. 4.1) instead of a network
+  bool closed_yield = false;           // yield: G = identity (Eq. ostwald_potential) instead of a network
   // per-phase event profiling of gedmg_assemble
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;     // 5 events per timed assembly

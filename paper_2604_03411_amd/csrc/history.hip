@@ -36,41 +36,70 @@ template <int H, int L>
 __device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net, double yN0, double q,
                                                   double& dN, const double* __restrict__ et,
                                                   const double* __restrict__ lt) {
-  const int stride = H * H + 2 * H;  // Wz, Wx, b of one hidden layer
-  const int owz = 2 * H + (L - 1) * stride;
-  double pN = 0.0, pD = 0.0;
-  if constexpr (L == 1) {
-    // a single hidden layer: all of its weights fit in registers, and the
-    // unrolled form lets the neurons' instruction streams interleave
-    double z[H], zt[H];
-#pragma unroll
-    for (int n = 0; n < H; ++n) {
-      const double w = net[n];
-      double s;
-      z[n] = softplus_tab(fma(w, q, net[H + n]), s, et, lt);
-      zt[n] = s * w;
-    }
-#pragma unroll
-    for (int n = 0; n < H; ++n) {
-      pN = fma(net[owz + n], z[n], pN);
-      pD = fma(net[owz + n], zt[n], pD);
-    }
+  if constexpr (L == 0) {  // closed-form model: G(q) = q (Eq. ostwald_potential)
+    dN = 1.0;
+    return q;
   } else {
-    double z[H], zt[H];
+    const int stride = H * H + 2 * H;  // Wz, Wx, b of one hidden layer
+    const int owz = 2 * H + (L - 1) * stride;
+    double pN = 0.0, pD = 0.0;
+    if constexpr (L == 1) {
+      // a single hidden layer: all of its weights fit in registers, and the
+      // unrolled form lets the neurons' instruction streams interleave
+      double z[H], zt[H];
 #pragma unroll
-    for (int n = 0; n < H; ++n) {
-      const double w = net[n];
-      double s;
-      z[n] = softplus_tab(fma(w, q, net[H + n]), s, et, lt);
-      zt[n] = s * w;
-    }
+      for (int n = 0; n < H; ++n) {
+        const double w = net[n];
+        double s;
+        z[n] = softplus_tab(fma(w, q, net[H + n]), s, et, lt);
+        zt[n] = s * w;
+      }
 #pragma unroll
-    for (int k = 1; k < L - 1; ++k) {
-      const double* Wz = net + 2 * H + (k - 1) * stride;
+      for (int n = 0; n < H; ++n) {
+        pN = fma(net[owz + n], z[n], pN);
+        pD = fma(net[owz + n], zt[n], pD);
+      }
+    } else {
+      double z[H], zt[H];
+#pragma unroll
+      for (int n = 0; n < H; ++n) {
+        const double w = net[n];
+        double s;
+        z[n] = softplus_tab(fma(w, q, net[H + n]), s, et, lt);
+        zt[n] = s * w;
+      }
+#pragma unroll
+      for (int k = 1; k < L - 1; ++k) {
+        const double* Wz = net + 2 * H + (k - 1) * stride;
+        const double* Wx = Wz + H * H;
+        const double* b = Wx + H;
+        double zn[H], ztn[H];
+#pragma unroll
+        for (int n = 0; n < H; ++n) {
+          double acc = fma(Wx[n], q, b[n]);
+          double acct = Wx[n];
+#pragma unroll
+          for (int m = 0; m < H; ++m) {
+            acc = fma(Wz[n * H + m], z[m], acc);
+            acct = fma(Wz[n * H + m], zt[m], acct);
+          }
+          double s;
+          zn[n] = softplus_tab(acc, s, et, lt);
+          ztn[n] = s * acct;
+        }
+#pragma unroll
+        for (int n = 0; n < H; ++n) {
+          z[n] = zn[n];
+          zt[n] = ztn[n];
+        }
+      }
+      // last hidden layer: one neuron per iteration of a rolled loop, so its
+      // weight row is loaded when needed rather than held in registers, and its
+      // activation goes straight into the output sums
+      const double* Wz = net + 2 * H + (L - 2) * stride;
       const double* Wx = Wz + H * H;
       const double* b = Wx + H;
-      double zn[H], ztn[H];
-#pragma unroll
+#pragma unroll 1
       for (int n = 0; n < H; ++n) {
         double acc = fma(Wx[n], q, b[n]);
         double acct = Wx[n];
@@ -80,39 +109,15 @@ __device__ __forceinline__ double yield_eval_lane(const double* __restrict__ net
           acct = fma(Wz[n * H + m], zt[m], acct);
         }
         double s;
-        zn[n] = softplus_tab(acc, s, et, lt);
-        ztn[n] = s * acct;
-      }
-#pragma unroll
-      for (int n = 0; n < H; ++n) {
-        z[n] = zn[n];
-        zt[n] = ztn[n];
+        const double zv = softplus_tab(acc, s, et, lt);
+        pN = fma(net[owz + n], zv, pN);
+        pD = fma(net[owz + n], s * acct, pD);
       }
     }
-    // last hidden layer: one neuron per iteration of a rolled loop, so its
-    // weight row is loaded when needed rather than held in registers, and its
-    // activation goes straight into the output sums
-    const double* Wz = net + 2 * H + (L - 2) * stride;
-    const double* Wx = Wz + H * H;
-    const double* b = Wx + H;
-#pragma unroll 1
-    for (int n = 0; n < H; ++n) {
-      double acc = fma(Wx[n], q, b[n]);
-      double acct = Wx[n];
-#pragma unroll
-      for (int m = 0; m < H; ++m) {
-        acc = fma(Wz[n * H + m], z[m], acc);
-        acct = fma(Wz[n * H + m], zt[m], acct);
-      }
-      double s;
-      const double zv = softplus_tab(acc, s, et, lt);
-      pN = fma(net[owz + n], zv, pN);
-      pD = fma(net[owz + n], s * acct, pD);
-    }
+    const double wx = net[owz + H];
+    dN = pD + wx;
+    return pN + wx * q + net[owz + H + 1] - yN0;
   }
-  const double wx = net[owz + H];
-  dN = pD + wx;
-  return pN + wx * q + net[owz + H + 1] - yN0;
 }
 
 // The same network in FP32 with the hardware exponential, logarithm and
@@ -202,6 +207,12 @@ __device__ __forceinline__ float yield_eval_lane_f32(const double* __restrict__ 
 
 // FP32 pre-solve iterations (not counted against max_local).
 constexpr int kF32Iters = 12;
+// Acceptance of the FP64 local Newton iteration: a correction |dk| below
+// kAcceptRel max(1, |k|) is applied without a further network evaluation (the
+// error of k + dk is the curvature times dk^2, far below rounding); the
+// bracket [lo, hi] counts as closed below kBracketRel max(1, |k|).
+constexpr double kAcceptRel = 1e-13;
+constexpr double kBracketRel = 1e-15;
 
 template <int YH, int YL>
 __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs a) {
@@ -213,6 +224,12 @@ __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs 
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= a.nq) return;
   const Material M = a.m;
+  if (a.frozen) {  // staggered scheme: the history stays at kappa_n during the global solve
+    a.kappa_out[g] = a.kappa_n[g];
+    a.sens[g * 2] = 0.0;
+    a.sens[g * 2 + 1] = 0.0;
+    return;
+  }
   // psi_e at the point (Eq. dd_0): mu (N(x) - N(0) - n0 x3) + lam (J + 1/J - 2)^2
   const double x3 = a.x[g * 3 + 2];
   const double Jd = 1.0 + x3;
@@ -296,10 +313,8 @@ __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs 
       // is accepted rather than bisected away from.
       const double dq = gbe * inv_f * (-1.0 + ((k > M.kd) ? M.eta * (phi - k) : 0.0));
       const double dk = div_d(-h, dNy * dq - 1.0);
-      const double tol = 1e-15 * fmax(1.0, fabs(k));
-      // a correction this small leaves k + dk off by the curvature times dk^2,
-      // far below rounding, so it is accepted without a further evaluation
-      if (fabs(dk) <= 1e-13 * fmax(1.0, fabs(k))) {
+      const double bracket_tol = kBracketRel * fmax(1.0, fabs(k));
+      if (fabs(dk) <= kAcceptRel * fmax(1.0, fabs(k))) {
         k = fmin(fmax(k + dk, lo), hi);
         conv = true;
         break;
@@ -317,7 +332,7 @@ __global__ __launch_bounds__(256, YL <= 2 ? 2 : 1) void history_kernel(HistArgs 
       const double qk = psi_e + gbe * (phi - k) * inv_f;
       h = yield_eval_lane<YH, YL>(a.ynet, a.yN0, qk, dNy, et, lt) - k;
       if (h > 0.0) lo = k; else hi = k;
-      if (h == 0.0 || !(hi - lo > tol)) { conv = true; break; }
+      if (h == 0.0 || !(hi - lo > bracket_tol)) { conv = true; break; }
     }
     if (!conv) a.status[0] = GEDMG_E_LOCAL_NOCONV;
     kap = k;
@@ -342,7 +357,8 @@ hipError_t launch_history(const HistArgs& a, int yH, hipStream_t s) {
   const int blocks = (int)((a.nq + 255) / 256);
   if (blocks == 0) return hipSuccess;
   const dim3 g(blocks), b(256);
-  if (yH == 16 && a.yL == 1) hipLaunchKernelGGL((history_kernel<16, 1>), g, b, 0, s, a);
+  if (a.yL == 0) hipLaunchKernelGGL((history_kernel<0, 0>), g, b, 0, s, a);
+  else if (yH == 16 && a.yL == 1) hipLaunchKernelGGL((history_kernel<16, 1>), g, b, 0, s, a);
   else if (yH == 16 && a.yL == 2) hipLaunchKernelGGL((history_kernel<16, 2>), g, b, 0, s, a);
   else if (yH == 16 && a.yL == 3) hipLaunchKernelGGL((history_kernel<16, 3>), g, b, 0, s, a);
   else if (yH == 32 && a.yL == 1) hipLaunchKernelGGL((history_kernel<32, 1>), g, b, 0, s, a);

@@ -83,6 +83,7 @@ NetRef pack_network(const NetLayout& lay, const double* raw, std::vector<double>
 }
 
 hipError_t launch_energy_jet(int precision, int H, const JetArgs& a, hipStream_t s, int num_cu) {
+  if (a.L == 0) return launch_closed_form_jet(a, s);  // no layer products: FP64 whatever the precision
   if (precision == GEDMG_FP64) return launch_energy_jet_f64(H, a, s, num_cu);
   return launch_energy_jet_lp(precision, H, a, s, num_cu);
 }
@@ -143,9 +144,11 @@ uint16_t to_f16(double v) {
 }
 
 int check_net(gedmg_ctx* c, const gedmg_icnn* n, int n_in, bool energy) {
-  if (!n || !n->theta) { c->err = "null network descriptor"; return GEDMG_E_ARG; }
+  if (!n) { c->err = "null network descriptor"; return GEDMG_E_ARG; }
   if (n->n_in != n_in) { c->err = "network input count not supported"; return GEDMG_E_SHAPE; }
-  if (n->n_hidden < 1 || n->n_hidden > kMaxHidden) { c->err = "n_hidden must be 1..3"; return GEDMG_E_SHAPE; }
+  if (n->n_hidden == 0) return GEDMG_OK;  // closed-form model, no parameters
+  if (!n->theta) { c->err = "null network parameters"; return GEDMG_E_ARG; }
+  if (n->n_hidden < 1 || n->n_hidden > kMaxHidden) { c->err = "n_hidden must be 0..3"; return GEDMG_E_SHAPE; }
   const int H = n->width;
   const bool ok = energy ? (H == 16 || H == 32 || H == 64) : (H == 16 || H == 32);
   if (!ok) { c->err = "network width not supported"; return GEDMG_E_SHAPE; }
@@ -153,6 +156,8 @@ int check_net(gedmg_ctx* c, const gedmg_icnn* n, int n_in, bool energy) {
 }
 
 int upload_params(gedmg_ctx* c, const double* te, const double* ty) {
+  if (c->closed_energy) te = nullptr;  // closed-form models have no parameters
+  if (c->closed_yield) ty = nullptr;
   if (te) {
     std::copy(te, te + c->elay.n_raw, c->eraw.begin());
     std::vector<double> p;
@@ -212,6 +217,81 @@ int dalloc(gedmg_ctx* c, T** p, size_t n) {
 }
 
 }  // namespace
+
+namespace gedmg {
+
+__global__ void fill_zero_kernel(double* p, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+Material element_material(const gedmg_ctx* c) {
+  Material m = c->mat;
+  if (c->closed_energy) {  // the jet already is psi_NH: unit scale, no separate volumetric term
+    m.mu = 1.0;
+    m.lam = 0.0;
+  }
+  return m;
+}
+
+int assemble_impl(gedmg_ctx* c, const double* u, const double* phi, const double* kappa_n, int precision,
+                  double* R, double* K_vals, double* kappa_trial, const AssembleScratch& sc, bool fill_kernel) {
+  if (!u || !phi || !kappa_n || !R || !kappa_trial) { c->err = "null array argument"; return GEDMG_E_ARG; }
+  if (precision != GEDMG_FP64 && precision != GEDMG_BF16 && precision != GEDMG_FP16) {
+    c->err = "unknown precision";
+    return GEDMG_E_ARG;
+  }
+  if (reinterpret_cast<uintptr_t>(K_vals) % 16 != 0) {
+    c->err = "K_vals must be 16-byte aligned";
+    return GEDMG_E_ARG;
+  }
+  constexpr int NEV = 6;
+  hipEvent_t ev[NEV] = {};
+  const bool prof = c->prof && !fill_kernel;
+  if (prof) {
+    for (int i = 0; i < NEV; ++i) {
+      GEDMG_HIP(c, hipEventCreate(&ev[i]));
+      c->prof_ev.push_back(ev[i]);
+    }
+    c->prof_calls++;
+    GEDMG_HIP(c, hipEventRecord(ev[0], c->stream));
+  }
+  if (fill_kernel) {
+    const long nb = std::min<long>((c->ndof + 255) / 256, 2048);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)std::max(nb, 1L)), dim3(256), 0, c->stream, R, c->ndof);
+    GEDMG_HIP(c, hipGetLastError());
+  } else {
+    GEDMG_HIP(c, hipMemsetAsync(R, 0, sizeof(double) * c->ndof, c->stream));
+  }
+  if (prof) GEDMG_HIP(c, hipEventRecord(ev[1], c->stream));
+  KinArgs ka{c->dX, c->dconn, u, phi, c->n_nodes, c->n_elems, sc.x, sc.phiq, c->dstatus};
+  GEDMG_HIP(c, launch_qp_inputs(c->dim, ka, c->stream));
+  if (prof) GEDMG_HIP(c, hipEventRecord(ev[2], c->stream));
+  const int64_t nq = (int64_t)c->n_elems * c->nqp;
+  JetArgs ja{sc.x, sc.jet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16, c->dwop,
+             (int)nq, c->elay.L, K_vals ? 1 : 0, c->dmtab, c->mat.mu, c->mat.lam};
+  GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
+  if (prof) GEDMG_HIP(c, hipEventRecord(ev[3], c->stream));
+  const Material em = element_material(c);
+  HistArgs ha{sc.x, sc.jet, sc.phiq, kappa_n, c->dynet, kappa_trial, sc.sens, c->dstatus, (long)nq,
+              em, c->eref.n0, c->yref.N0, c->ylay.L, c->max_local, c->frozen_history, c->dmtab};
+  GEDMG_HIP(c, launch_history(ha, c->ylay.H, c->stream));
+  if (prof) GEDMG_HIP(c, hipEventRecord(ev[4], c->stream));
+  ElemArgs ea{};
+  ea.Xs = c->dXs; ea.conn_s = c->dconn_s; ea.perm = c->dperm; ea.seg = c->dseg;
+  ea.u = u; ea.phi = phi; ea.jet = sc.jet; ea.kappa = kappa_trial; ea.sens = sc.sens;
+  ea.R = R; ea.K = K_vals; ea.status = c->dstatus;
+  ea.n_nodes = c->n_nodes; ea.n_elems = c->n_elems;
+  ea.m = em; ea.n0 = c->eref.n0;
+  for (size_t k = 0; k + 1 < c->color_begin.size(); ++k) {
+    ea.e_begin = c->color_begin[k];
+    ea.e_end = c->color_begin[k + 1];
+    GEDMG_HIP(c, launch_element(c->dim, K_vals != nullptr, ea, c->stream));
+  }
+  if (prof) GEDMG_HIP(c, hipEventRecord(ev[5], c->stream));
+  return GEDMG_OK;
+}
+
+}  // namespace gedmg
 
 static void prof_clear(gedmg_ctx* c);
 
@@ -376,9 +456,13 @@ int gedmg_create(gedmg_ctx** out, const gedmg_mesh* mesh, const gedmg_material* 
   GEDMG_HIP(c, hipMemcpy(c->dcol, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
   GEDMG_HIP(c, hipMemset(c->dstatus, 0, 4 * sizeof(int)));
 
-  // ---- networks
-  c->elay = make_layout_hd(3, energy->width, energy->n_hidden, energy->monotone_mask);
-  c->ylay = make_layout_hd(1, yield->width, yield->n_hidden, yield->monotone_mask);
+  // ---- networks (n_hidden == 0: the closed-form model of Sec. 4.1, no parameters)
+  c->closed_energy = energy->n_hidden == 0;
+  c->closed_yield = yield->n_hidden == 0;
+  c->elay = c->closed_energy ? make_layout_hd(3, 0, 0, 0)
+                             : make_layout_hd(3, energy->width, energy->n_hidden, energy->monotone_mask);
+  c->ylay = c->closed_yield ? make_layout_hd(1, 0, 0, 0)
+                            : make_layout_hd(1, yield->width, yield->n_hidden, yield->monotone_mask);
   c->eraw.assign(c->elay.n_raw, 0.0);
   c->yraw.assign(c->ylay.n_raw, 0.0);
   const size_t wlp = (size_t)std::max(c->elay.L - 1, 1) * c->elay.H * (c->elay.H + 8);
@@ -424,52 +508,8 @@ int gedmg_csr(gedmg_ctx* ctx, int64_t* n_rows, int64_t* nnz, const int32_t** row
 int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const double* kappa_n,
                    int precision, double* R, double* K_vals, double* kappa_trial) {
   if (!c) return GEDMG_E_ARG;
-  if (!u || !phi || !kappa_n || !R || !kappa_trial) { c->err = "null array argument"; return GEDMG_E_ARG; }
-  if (precision != GEDMG_FP64 && precision != GEDMG_BF16 && precision != GEDMG_FP16) {
-    c->err = "unknown precision";
-    return GEDMG_E_ARG;
-  }
-  if (reinterpret_cast<uintptr_t>(K_vals) % 16 != 0) {
-    c->err = "K_vals must be 16-byte aligned";
-    return GEDMG_E_ARG;
-  }
-  constexpr int NEV = 6;
-  hipEvent_t ev[NEV] = {};
-  if (c->prof) {
-    for (int i = 0; i < NEV; ++i) {
-      GEDMG_HIP(c, hipEventCreate(&ev[i]));
-      c->prof_ev.push_back(ev[i]);
-    }
-    c->prof_calls++;
-    GEDMG_HIP(c, hipEventRecord(ev[0], c->stream));
-  }
-  GEDMG_HIP(c, hipMemsetAsync(R, 0, sizeof(double) * c->ndof, c->stream));
-  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[1], c->stream));
-  KinArgs ka{c->dX, c->dconn, u, phi, c->n_nodes, c->n_elems, c->dx, c->dphiq, c->dstatus};
-  GEDMG_HIP(c, launch_qp_inputs(c->dim, ka, c->stream));
-  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[2], c->stream));
-  const int64_t nq = (int64_t)c->n_elems * c->nqp;
-  JetArgs ja{c->dx, c->djet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16, c->dwop,
-             (int)nq, c->elay.L, K_vals ? 1 : 0, c->dmtab};
-  GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
-  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[3], c->stream));
-  HistArgs ha{c->dx, c->djet, c->dphiq, kappa_n, c->dynet, kappa_trial, c->dsens, c->dstatus, (long)nq,
-              c->mat, c->eref.n0, c->yref.N0, c->ylay.L, c->max_local, c->dmtab};
-  GEDMG_HIP(c, launch_history(ha, c->ylay.H, c->stream));
-  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[4], c->stream));
-  ElemArgs ea{};
-  ea.Xs = c->dXs; ea.conn_s = c->dconn_s; ea.perm = c->dperm; ea.seg = c->dseg;
-  ea.u = u; ea.phi = phi; ea.jet = c->djet; ea.kappa = kappa_trial; ea.sens = c->dsens;
-  ea.R = R; ea.K = K_vals; ea.status = c->dstatus;
-  ea.n_nodes = c->n_nodes; ea.n_elems = c->n_elems;
-  ea.m = c->mat; ea.n0 = c->eref.n0;
-  for (size_t k = 0; k + 1 < c->color_begin.size(); ++k) {
-    ea.e_begin = c->color_begin[k];
-    ea.e_end = c->color_begin[k + 1];
-    GEDMG_HIP(c, launch_element(c->dim, K_vals != nullptr, ea, c->stream));
-  }
-  if (c->prof) GEDMG_HIP(c, hipEventRecord(ev[5], c->stream));
-  return GEDMG_OK;
+  const AssembleScratch sc{c->dx, c->djet, c->dphiq, c->dsens};
+  return assemble_impl(c, u, phi, kappa_n, precision, R, K_vals, kappa_trial, sc, false);
 }
 
 static void prof_clear(gedmg_ctx* c) {
@@ -511,7 +551,7 @@ int gedmg_energy_jet(gedmg_ctx* c, const double* x, int64_t n, int precision, do
     return GEDMG_E_ARG;
   }
   JetArgs ja{x, jet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16, c->dwop, (int)n,
-             c->elay.L, 1, c->dmtab};
+             c->elay.L, 1, c->dmtab, c->mat.mu, c->mat.lam};
   GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
   return GEDMG_OK;
 }

@@ -23,6 +23,22 @@ namespace gedmg {
 constexpr int kRedBlocks = 512;  // blocks of every reduction kernel
 constexpr int kThreads = 256;
 
+gedmg_solver_opts default_solver_opts() {
+  gedmg_solver_opts o{};
+  o.max_newton = 25;
+  o.max_krylov = 20000;
+  o.max_local = 100;
+  o.newton_rtol = 1e-10;
+  o.newton_atol = 0.0;
+  o.krylov_rtol = 1e-12;
+  o.krylov_forcing = 1;
+  o.refine_max = 10;
+  o.refine_rtol = 1e-8;
+  o.scheme = GEDMG_MONOLITHIC;
+  o.newton_rscale = 1.0;
+  return o;
+}
+
 // Device scalar slots (doubles).
 // S_FLAG + 1 holds sums read back by the host; S_E = chi . K chi and S_CC =
 // (chi . r) / S_E, the coarse coefficient of the current residual.
@@ -682,8 +698,8 @@ int solver_solve_free(gedmg_ctx* c, double* A, const gedmg_dirichlet* bc, const 
 }  // namespace gedmg
 
 extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const gedmg_solver_opts* opts_in,
-                                 int precision, double* u, double* phi, double* kappa,
-                                 const int32_t* reaction_dofs, int32_t n_reaction,
+                                 int precision, const double* predictor_du, double* u, double* phi,
+                                 double* kappa, const int32_t* reaction_dofs, int32_t n_reaction,
                                  gedmg_newton_report* rep) {
   if (!c) return GEDMG_E_ARG;
   if (!bc || !u || !phi || !kappa || (bc->n > 0 && (!bc->dof || !bc->value)) || bc->n < 0 ||
@@ -695,11 +711,34 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
     c->err = "unknown precision";
     return GEDMG_E_ARG;
   }
-  gedmg_solver_opts o{25, 20000, 100, 1e-10, 0.0, 1e-12, 1};
+  gedmg_solver_opts o = default_solver_opts();
   if (opts_in) o = *opts_in;
-  if (o.max_local <= 0 || o.max_newton < 0 || o.max_krylov <= 0) {
+  if (o.max_local <= 0 || o.max_newton < 0 || o.max_krylov <= 0 || o.refine_max < 0) {
     c->err = "solver limits must be positive";
     return GEDMG_E_ARG;
+  }
+  if (!(o.newton_rscale >= 0.0)) {
+    c->err = "newton_rscale must be non-negative";
+    return GEDMG_E_ARG;
+  }
+  if (o.scheme != GEDMG_MONOLITHIC && o.scheme != GEDMG_STAGGERED) {
+    c->err = "unknown solution scheme";
+    return GEDMG_E_ARG;
+  }
+  if (n_reaction < 0) {
+    c->err = "negative reaction dof count";
+    return GEDMG_E_ARG;
+  }
+  // reaction dofs must be in range (checked on the host, before any work)
+  if (n_reaction > 0) {
+    std::vector<int32_t> rd(n_reaction);
+    GH(hipMemcpyAsync(rd.data(), reaction_dofs, sizeof(int32_t) * n_reaction, hipMemcpyDeviceToHost, c->stream));
+    GH(hipStreamSynchronize(c->stream));
+    for (int32_t d : rd)
+      if (d < 0 || d >= c->ndof) {
+        c->err = "reaction dof index out of range";
+        return GEDMG_E_ARG;
+      }
   }
   c->max_local = o.max_local;
   gedmg_newton_report local{};
@@ -714,6 +753,11 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
   // backups for rollback
   GH(hipMemcpyAsync(w.ub, u, sizeof(double) * c->dim * c->n_nodes, hipMemcpyDeviceToDevice, c->stream));
   GH(hipMemcpyAsync(w.phib, phi, sizeof(double) * c->n_nodes, hipMemcpyDeviceToDevice, c->stream));
+  if (predictor_du) {
+    const long nu = (long)c->dim * c->n_nodes;
+    hipLaunchKernelGGL(add_kernel, dim3((nu + 255) / 256), dim3(256), 0, c->stream, u, predictor_du, nu);
+    GH(hipGetLastError());
+  }
   GH(hipMemsetAsync(w.mask, 0, n, c->stream));
   GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
   if (bc->n > 0) {
@@ -737,8 +781,15 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
     return code;
   };
   const bool mixed = precision != GEDMG_FP64;
+  const int max_it = o.max_newton + (mixed ? o.refine_max : 0);
+  // staggered scheme: every assembly of the global solve holds kappa_n
+  struct FrozenGuard {
+    gedmg_ctx* c;
+    ~FrozenGuard() { c->frozen_history = 0; }
+  } guard{c};
+  c->frozen_history = o.scheme == GEDMG_STAGGERED ? 1 : 0;
   double res0 = -1.0;
-  for (int it = 0; it <= o.max_newton; ++it) {
+  for (int it = 0; it <= max_it; ++it) {
     // residual (FP64) and tangent (FP64 or mixed)
     if (mixed) {
       if ((rc = gedmg_assemble(c, u, phi, kappa, precision, w.Rmp, w.K, w.ktmp))) return rollback(rc);
@@ -756,8 +807,14 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
     r.newton_iters = it;
     if (!std::isfinite(res)) { c->err = "non-finite residual"; return rollback(GEDMG_E_NONFINITE); }
     if (res0 < 0.0) res0 = res;
-    if (res <= std::max(o.newton_rtol * std::max(1.0, res0), o.newton_atol)) {
+    if (res <= std::max(o.newton_rtol * std::max(o.newton_rscale, res0), o.newton_atol)) {
       // converged: commit the history and report
+      if (o.scheme == GEDMG_STAGGERED) {
+        // the local update at the converged fields (residual of this pass unused)
+        c->frozen_history = 0;
+        if ((rc = gedmg_assemble(c, u, phi, kappa, GEDMG_FP64, w.Rmp, nullptr, w.kt))) return rollback(rc);
+        if ((rc = gedmg_status(c))) return rollback(rc);
+      }
       GH(hipMemcpyAsync(w.ktmp, kappa, sizeof(double) * w.nq, hipMemcpyDeviceToDevice, c->stream));
       GH(hipMemcpyAsync(kappa, w.kt, sizeof(double) * w.nq, hipMemcpyDeviceToDevice, c->stream));
       hipLaunchKernelGGL(count_growth_kernel, dim3(gr), dim3(kThreads), 0, c->stream, kappa, w.ktmp, w.nq,
@@ -775,13 +832,14 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
       r.status = GEDMG_OK;
       return GEDMG_OK;
     }
-    if (it == o.max_newton) break;
+    if (it == max_it) break;
     hipLaunchKernelGGL(mask_matrix_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, w.K, c->drowptr,
                        c->dcol, w.mask, w.dinv, n);
     GH(hipGetLastError());
     int its = 0;
-    const double eta =
+    double eta =
         o.krylov_forcing ? std::max(o.krylov_rtol, std::min(1e-3, res / std::max(res0, 1e-300))) : o.krylov_rtol;
+    if (mixed) eta = std::max(eta, o.refine_rtol);
     rc = krylov(c, w, w.K, o.max_krylov, eta, &its);
     r.krylov_iters_total += its;
     if (rc) return rollback(rc);

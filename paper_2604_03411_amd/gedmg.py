@@ -55,7 +55,31 @@ class Dirichlet(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("max_krylov", C.c_int32), ("max_local", C.c_int32),
                 ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("krylov_rtol", C.c_double),
-                ("krylov_forcing", C.c_int32)]
+                ("krylov_forcing", C.c_int32), ("refine_max", C.c_int32), ("refine_rtol", C.c_double),
+                ("scheme", C.c_int32), ("newton_rscale", C.c_double)]
+
+SCHEMES = {"monolithic": 0, "staggered": 1}
+
+
+# Defaults of gedmg_solver_opts (include/gedmg.h); the bindings pass every field.
+SOLVER_DEFAULTS = dict(max_newton=25, max_krylov=20000, max_local=100, newton_rtol=1e-10, newton_atol=0.0,
+                       krylov_rtol=1e-12, krylov_forcing=True, refine_max=10, refine_rtol=1e-8,
+                       scheme="monolithic", newton_rscale=1.0)
+
+
+def solver_opts(**kw):
+    unknown = set(kw) - set(SOLVER_DEFAULTS)
+    if unknown:
+        raise GedmgError(-1, f"unknown solver options {sorted(unknown)}")
+    o = dict(SOLVER_DEFAULTS, **kw)
+    sch = o["scheme"]
+    if isinstance(sch, str):
+        if sch not in SCHEMES:
+            raise GedmgError(-1, f"unknown scheme {sch!r}")
+        sch = SCHEMES[sch]
+    return SolverOpts(int(o["max_newton"]), int(o["max_krylov"]), int(o["max_local"]), float(o["newton_rtol"]),
+                      float(o["newton_atol"]), float(o["krylov_rtol"]), 1 if o["krylov_forcing"] else 0,
+                      int(o["refine_max"]), float(o["refine_rtol"]), int(sch), float(o["newton_rscale"]))
 
 
 class NewtonReport(C.Structure):
@@ -91,17 +115,19 @@ def lib():
         L.gedmg_status.argtypes = [vp]
         L.gedmg_energy_jet.argtypes = [vp, vp, i64, C.c_int, vp]
         L.gedmg_profile.argtypes = [vp, C.c_int]
+        if hasattr(L, "gedmg_probe_mfma"):
+            L.gedmg_probe_mfma.argtypes = [vp, i32, i32, vp]
         L.gedmg_profile_read.argtypes = [vp, C.POINTER(dp), C.POINTER(i32)]
         if hasattr(L, "gedmg_newton_step"):
             L.gedmg_newton_step.argtypes = [vp, C.POINTER(Dirichlet), C.POINTER(SolverOpts), C.c_int,
-                                            vp, vp, vp, vp, i32, C.POINTER(NewtonReport)]
+                                            vp, vp, vp, vp, vp, i32, C.POINTER(NewtonReport)]
         if hasattr(L, "gedmg_adjoint"):
             L.gedmg_adjoint.argtypes = [vp, i32, C.POINTER(Dirichlet), vp, vp, i32, vp, i32,
                                         C.POINTER(SolverOpts), vp, vp, vp, C.POINTER(dp), C.POINTER(dp),
                                         C.POINTER(dp), C.POINTER(AdjointReport)]
         for name in ("gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
                      "gedmg_assemble", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
-                     "gedmg_energy_jet", "gedmg_profile", "gedmg_profile_read"):
+                     "gedmg_energy_jet", "gedmg_profile", "gedmg_profile_read", "gedmg_probe_mfma"):
             if hasattr(L, name):
                 getattr(L, name).restype = C.c_int
         _lib = L
@@ -110,7 +136,18 @@ def lib():
 
 EXPORTED = ("gedmg_last_error", "gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
             "gedmg_assemble", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
-            "gedmg_energy_jet", "gedmg_profile", "gedmg_profile_read")
+            "gedmg_energy_jet", "gedmg_profile", "gedmg_profile_read", "gedmg_probe_mfma")
+
+
+def probe_mfma(blocks, iters):
+    """Launch the matrix-core calibration probe on the current stream; returns
+    the number of FP64 16x16x4 products issued."""
+    sink = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    rc = lib().gedmg_probe_mfma(_dptr(sink), int(blocks), int(iters), _stream())
+    if rc != 0:
+        raise GedmgError(rc, "gedmg_probe_mfma failed")
+    torch.cuda.synchronize()
+    return blocks * 4 * 4 * iters
 
 
 def _hip():
@@ -127,6 +164,26 @@ def _stream():
 
 def _f64(t, dev):
     return torch.as_tensor(t, dtype=torch.float64, device=dev).contiguous()
+
+
+def _check_array(t, numel, dev, name, dtype=torch.float64):
+    """A caller's device array: contiguous, of the given dtype, size and device
+    (checked here, before any launch, so that a wrong buffer cannot make a
+    kernel index past its end)."""
+    if not isinstance(t, torch.Tensor):
+        raise GedmgError(-1, f"{name} must be a torch tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel or t.device != dev:
+        raise GedmgError(-1, f"{name} must be a contiguous {dtype} tensor of {numel} elements on {dev} "
+                             f"(got {t.dtype}, {t.numel()} elements, contiguous={t.is_contiguous()}, {t.device})")
+    return t
+
+
+def _dof_index_array(idx, ndof, dev, name):
+    """Host-checked int32 device array of dof indices in [0, ndof)."""
+    a = np.asarray(idx.detach().cpu().numpy() if isinstance(idx, torch.Tensor) else idx).reshape(-1)
+    if a.size and (not np.issubdtype(a.dtype, np.integer) or a.min() < 0 or a.max() >= ndof):
+        raise GedmgError(-1, f"{name}: dof indices must be integers in [0, {ndof})")
+    return torch.as_tensor(a.astype(np.int32), device=dev).contiguous()
 
 
 class Context:
@@ -216,6 +273,11 @@ class Context:
     def fields(self, u, phi, kappa):
         return _f64(u, self.dev), _f64(phi, self.dev), _f64(kappa, self.dev)
 
+    def _check_fields(self, u, phi, kappa):
+        _check_array(u, self.dim * self.n_nodes, self.dev, "u")
+        _check_array(phi, self.n_nodes, self.dev, "phi")
+        _check_array(kappa, self.n_elems * self.nqp, self.dev, "kappa")
+
     def assemble(self, u, phi, kappa, precision="fp64", tangent=True, out=None):
         """Returns (R [ndof], K_vals [nnz] or None, kappa_trial [n_elems, nqp]) on the device."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -225,17 +287,23 @@ class Context:
             kt = torch.empty(self.n_elems, self.nqp, dtype=torch.float64, device=self.dev)
         else:
             R, K, kt = out
-        for t, n in ((u, self.dim * self.n_nodes), (phi, self.n_nodes), (kappa, self.n_elems * self.nqp)):
-            if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n or t.device != self.dev:
-                raise GedmgError(-1, "fields must be contiguous float64 device tensors of the mesh size")
-        self._check(lib().gedmg_assemble(self._h, _dptr(u), _dptr(phi), _dptr(kappa), prec,
-                                         _dptr(R), _dptr(K), _dptr(kt)))
+            _check_array(R, self.ndof, self.dev, "R")
+            if K is not None:
+                _check_array(K, self.nnz, self.dev, "K_vals")
+                if K.data_ptr() % 16:
+                    raise GedmgError(-1, "K_vals must be 16-byte aligned")
+            _check_array(kt, self.n_elems * self.nqp, self.dev, "kappa_trial")
+        self._check_fields(u, phi, kappa)
+        self._check(lib().gedmg_assemble(self._h, _dptr(u), _dptr(phi), _dptr(kappa), prec, _dptr(R), _dptr(K),
+                                         _dptr(kt)))
         return R, K, kt
 
     def energy_jet(self, x, precision="fp64"):
         """Energy-network jet [n, 10] at inputs x [n, 3] (device tensors)."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         x = _f64(x, self.dev)
+        if x.dim() != 2 or x.shape[1] != 3:
+            raise GedmgError(-1, f"x must be [n, 3] network inputs (got shape {tuple(x.shape)})")
         n = x.shape[0]
         jet = torch.empty(n, 10, dtype=torch.float64, device=self.dev)
         self._check(lib().gedmg_energy_jet(self._h, _dptr(x), n, prec, _dptr(jet)))
@@ -253,22 +321,30 @@ class Context:
                     calls=n.value)
 
     def newton_step(self, u, phi, kappa, bc_dofs, bc_vals, precision="fp64", reaction_dofs=None,
-                    max_newton=25, max_krylov=20000, max_local=100, newton_rtol=1e-10,
-                    newton_atol=0.0, krylov_rtol=1e-12, krylov_forcing=True, raise_on_error=True):
-        """One monolithic load step in place on (u, phi, kappa); returns the report as a dict."""
+                    predictor_du=None, raise_on_error=True, **solver):
+        """One load step in place on (u, phi, kappa): the predictor increment
+        predictor_du ([dim][n_nodes], or None) is added to u, the prescribed dofs
+        are set and Newton runs to convergence (gedmg_newton_step).  Solver
+        options are the fields of gedmg_solver_opts as keywords.  Returns the
+        report as a dict."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        dofs = torch.as_tensor(np.asarray(bc_dofs, dtype=np.int32), device=self.dev).contiguous()
-        vals = _f64(bc_vals, self.dev)
+        self._check_fields(u, phi, kappa)
+        dofs = _dof_index_array(bc_dofs, self.ndof, self.dev, "bc_dofs")
+        vals = _f64(bc_vals, self.dev).reshape(-1)
+        if vals.numel() != dofs.numel():
+            raise GedmgError(-1, "bc_vals must hold one value per prescribed dof")
         bc = Dirichlet(int(dofs.numel()), C.c_void_p(dofs.data_ptr()), C.c_void_p(vals.data_ptr()))
-        opts = SolverOpts(max_newton, max_krylov, max_local, newton_rtol, newton_atol, krylov_rtol,
-                          1 if krylov_forcing else 0)
+        opts = solver_opts(**solver)
+        pred = None
+        if predictor_du is not None:
+            pred = _check_array(_f64(predictor_du, self.dev), self.dim * self.n_nodes, self.dev, "predictor_du")
         rd = None
         nr = 0
         if reaction_dofs is not None:
-            rd = torch.as_tensor(np.asarray(reaction_dofs, dtype=np.int32), device=self.dev).contiguous()
+            rd = _dof_index_array(reaction_dofs, self.ndof, self.dev, "reaction_dofs")
             nr = int(rd.numel())
         rep = NewtonReport()
-        rc = lib().gedmg_newton_step(self._h, C.byref(bc), C.byref(opts), prec, _dptr(u), _dptr(phi),
+        rc = lib().gedmg_newton_step(self._h, C.byref(bc), C.byref(opts), prec, _dptr(pred), _dptr(u), _dptr(phi),
                                      _dptr(kappa), _dptr(rd), nr, C.byref(rep))
         out = dict(status=rc, newton_iters=rep.newton_iters, krylov_iters=rep.krylov_iters_total,
                    n_yielded_qp=rep.n_yielded_qp, reaction=rep.reaction,
@@ -287,22 +363,22 @@ class Context:
         keep = []
         bcs = (Dirichlet * n)()
         for i, (bd, bv) in enumerate(path.bcs):
-            d = torch.as_tensor(np.asarray(bd, dtype=np.int32), device=dv).contiguous()
-            v = _f64(bv, dv)
+            d = _dof_index_array(bd, self.ndof, dv, f"bc_dofs of step {i + 1}")
+            v = _f64(bv, dv).reshape(-1)
+            if v.numel() != d.numel():
+                raise GedmgError(-1, f"step {i + 1}: one value per prescribed dof")
             keep += [d, v]
             bcs[i] = Dirichlet(int(d.numel()), C.c_void_p(d.data_ptr()), C.c_void_p(v.data_ptr()))
         pred = None if path.predictor_du is None else _f64(path.predictor_du, dv)
         if pred is not None and pred.numel() != n * self.dim * self.n_nodes:
             raise GedmgError(-1, "predictor_du must hold n_steps x dim x n_nodes values")
-        rd = torch.as_tensor(np.asarray(path.reaction_dofs, dtype=np.int32), device=dv).contiguous()
+        rd = _dof_index_array(path.reaction_dofs, self.ndof, dv, "reaction_dofs")
         tg = _f64(path.targets, dv)
         if tg.numel() != n:
             raise GedmgError(-1, "one target per load step")
         u, phi, kap = (_f64(t, dv).clone() for t in (path.u0, path.phi0, path.kappa0))
-        o = path.opts
-        opts = SolverOpts(o.get("max_newton", 25), o.get("max_krylov", 20000), o.get("max_local", 100),
-                          o.get("newton_rtol", 1e-10), o.get("newton_atol", 0.0), o.get("krylov_rtol", 1e-12),
-                          1 if o.get("krylov_forcing", True) else 0)
+        self._check_fields(u, phi, kap)
+        opts = solver_opts(**path.opts)
         ge = np.zeros(self._te.size)
         gy = np.zeros(self._ty.size)
         loss = C.c_double()

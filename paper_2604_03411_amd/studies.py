@@ -1,0 +1,130 @@
+"""Load-path studies of the paper run through the gedmg library.
+
+These are drivers: they build the seeded study inputs (workloads), call
+gedmg_newton_step once per load increment and collect what the paper tracks.
+Every step of the method runs in the HIP library; the drivers only read back
+scalars (reaction, the largest history value) between increments.
+
+* single_element: Sec. 5.1, one 1 x 1 x 1 mm Hex8 element of the closed-form
+  model (compressible Neo-Hooke, G = identity) under uniaxial tension to
+  0.5 mm, local model, for a set of (eta_d, kappa_d).  Tracks the nominal
+  axial stress, kappa and d = 1 - f_d(kappa) against the stretch.
+* uniform_plate: Sec. 5.2, the 10 x 10 x 1 mm plate under uniaxial tension in
+  equal increments, with the local model (history updated after each step) or
+  the gradient-enhanced model under the monolithic or the staggered scheme, on
+  a coarse, a refined or a non-uniform mesh.  Stops when the largest damage
+  reaches d_stop (the paper's 0.995) or the solver fails.
+
+Usage:
+    python -m paper_2604_03411_amd.studies single-element
+    python -m paper_2604_03411_amd.studies plate [--steps 1000] [--total 80]
+(one JSON line per run on stdout).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+from . import gedmg as G  # noqa: E402
+
+RELATIVE = dict(newton_rtol=1e-12, newton_atol=0.0, newton_rscale=0.0, krylov_rtol=1e-14)
+
+
+def damage(kappa_max, mat):
+    """d = 1 - f_d(kappa) (Eq. degradation_function)."""
+    return 1.0 - math.exp(-mat["eta_d"] * max(kappa_max - mat["kappa_d"], 0.0))
+
+
+def single_element(eta_d, kappa_d, n_steps=50, total_disp=0.5):
+    case = W.single_element_case(eta_d=eta_d, kappa_d=kappa_d, n_steps=n_steps, total_disp=total_disp)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    du = W.uniaxial_increment(case)
+    rd = W.reaction_dofs(case)
+    rows = []
+    for n in range(1, n_steps + 1):
+        bd, bv = W.symmetric_tension_bc(case, n)
+        rep = ctx.newton_step(u, phi, kap, bd, bv, reaction_dofs=rd, predictor_du=du, scheme="staggered",
+                              **RELATIVE)
+        k = float(kap.max())
+        # nominal stress: reaction over the reference area (1 mm^2), with the
+        # history of the converged step (the global solve used kappa_{n-1})
+        fd_prev = 1.0 - damage(rows[-1]["kappa"], case.material) if rows else 1.0
+        p11 = rep["reaction"] / fd_prev * (1.0 - damage(k, case.material)) if fd_prev > 0.0 else 0.0
+        rows.append(dict(stretch=1.0 + total_disp * n / n_steps, kappa=k, d=damage(k, case.material), P11=p11,
+                         newton_iters=rep["newton_iters"]))
+    ctx.close()
+    return dict(study="single_element", eta_d=eta_d, kappa_d=kappa_d, steps=rows)
+
+
+def uniform_plate(mesh_kind="coarse", model="nonlocal", scheme="monolithic", n_steps=1000, total_disp=80.0,
+                  d_stop=0.995, max_steps=None):
+    """model: "nonlocal" (gradient-enhanced) or "local"; scheme: "monolithic"
+    or "staggered"."""
+    case = W.uniform_plate_case(mesh_kind, nonlocal_=(model == "nonlocal"), n_steps=n_steps,
+                                total_disp=total_disp)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    du = W.uniaxial_increment(case)
+    rd = W.reaction_dofs(case)
+    rows, status = [], "reached the last increment"
+    t0 = time.perf_counter()
+    for n in range(1, (max_steps or n_steps) + 1):
+        bd, bv = W.symmetric_tension_bc(case, n)
+        rep = ctx.newton_step(u, phi, kap, bd, bv, reaction_dofs=rd, predictor_du=du, scheme=scheme,
+                              raise_on_error=False, max_newton=40)
+        if rep["status"] != 0:
+            status = f"solver failed at increment {n} ({G.ERRORS.get(rep['status'], rep['status'])})"
+            break
+        k = float(kap.max())
+        d = damage(k, case.material)
+        rows.append(dict(disp=total_disp * n / n_steps, reaction=rep["reaction"], kappa_max=k, d_max=d,
+                         phi_max=float(phi.max()), newton_iters=rep["newton_iters"]))
+        if d >= d_stop:
+            status = f"reached d = {d_stop} at increment {n}"
+            break
+    ctx.close()
+    return dict(study="uniform_plate", mesh=mesh_kind, model=model, scheme=scheme, elements=case.mesh.n_elems,
+                increments=n_steps, total_disp=total_disp, status=status, wall_s=time.perf_counter() - t0,
+                steps=rows)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("study", choices=["single-element", "plate"])
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--total", type=float, default=None)
+    ap.add_argument("--every", type=int, default=1, help="keep every k-th step in the output")
+    args = ap.parse_args()
+    torch.cuda.set_device(0)
+    if args.study == "single-element":
+        for eta, kd in ((1.0, 1.0), (10.0, 1.0), (100.0, 1.0), (10.0, 0.0), (10.0, 2.0)):
+            r = single_element(eta, kd, args.steps or 50, args.total or 0.5)
+            r["steps"] = r["steps"][::args.every]
+            print(json.dumps(r), flush=True)
+        return
+    for mesh_kind in ("coarse", "refined", "nonuniform"):
+        for model, scheme in (("local", "staggered"), ("nonlocal", "monolithic"), ("nonlocal", "staggered")):
+            r = uniform_plate(mesh_kind, model, scheme, args.steps or 1000, args.total or 80.0)
+            last = r["steps"][-1] if r["steps"] else {}
+            print(f"[plate] {mesh_kind} {model} {scheme}: {r['status']}; last d_max {last.get('d_max')}, "
+                  f"{r['wall_s']:.1f} s", file=sys.stderr, flush=True)
+            r["steps"] = r["steps"][::args.every]
+            print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()

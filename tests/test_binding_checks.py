@@ -1,0 +1,83 @@
+"""The Python binding rejects malformed caller arrays before any library call
+(so a wrong buffer can never reach a kernel that would index past its end).
+Runs on the CPU: the context is a stub with no library handle, and every call
+below must raise GedmgError from the binding's own checks."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2604_03411_amd import gedmg as G
+
+
+def stub(dim=2, n_nodes=9, n_elems=4):
+    ctx = G.Context.__new__(G.Context)
+    ctx._h = None
+    ctx.dev = torch.device("cpu")
+    ctx.dim, ctx.n_nodes, ctx.n_elems = dim, n_nodes, n_elems
+    ctx.nqp = 4 if dim == 2 else 8
+    ctx.ndof = n_nodes * (dim + 1)
+    ctx.nnz = 81 * (dim + 1) ** 2
+    ctx._te = np.zeros(10)
+    ctx._ty = np.zeros(10)
+    return ctx
+
+
+def fields(ctx, dtype=torch.float64):
+    return (torch.zeros(ctx.dim * ctx.n_nodes, dtype=dtype), torch.zeros(ctx.n_nodes, dtype=dtype),
+            torch.zeros(ctx.n_elems * ctx.nqp, dtype=dtype))
+
+
+def expect_arg_error(fn):
+    with pytest.raises(G.GedmgError) as e:
+        fn()
+    assert e.value.code == -1
+
+
+def test_newton_step_rejects_wrong_field_dtype_and_size():
+    ctx = stub()
+    u, phi, kap = fields(ctx)
+    u32 = u.float()
+    expect_arg_error(lambda: ctx.newton_step(u32, phi, kap, [0], [0.0]))
+    expect_arg_error(lambda: ctx.newton_step(u[:-1], phi, kap, [0], [0.0]))
+    expect_arg_error(lambda: ctx.newton_step(u, phi[:3], kap, [0], [0.0]))
+    expect_arg_error(lambda: ctx.newton_step(u, phi, kap[::2], [0], [0.0]))
+
+
+def test_newton_step_rejects_out_of_range_dofs():
+    ctx = stub()
+    u, phi, kap = fields(ctx)
+    expect_arg_error(lambda: ctx.newton_step(u, phi, kap, [ctx.ndof], [0.0]))
+    expect_arg_error(lambda: ctx.newton_step(u, phi, kap, [-1], [0.0]))
+    expect_arg_error(lambda: ctx.newton_step(u, phi, kap, [0, 1], [0.0]))
+    expect_arg_error(lambda: ctx.newton_step(u, phi, kap, [0], [0.0], reaction_dofs=[ctx.ndof + 3]))
+    expect_arg_error(lambda: ctx.newton_step(u, phi, kap, [0], [0.0], predictor_du=np.zeros(5)))
+    expect_arg_error(lambda: ctx.newton_step(u, phi, kap, [0], [0.0], not_an_option=1))
+
+
+def test_assemble_rejects_wrong_outputs():
+    ctx = stub()
+    u, phi, kap = fields(ctx)
+    R = torch.zeros(ctx.ndof, dtype=torch.float64)
+    K = torch.zeros(ctx.nnz, dtype=torch.float64)
+    kt = torch.zeros(ctx.n_elems * ctx.nqp, dtype=torch.float64)
+    expect_arg_error(lambda: ctx.assemble(u, phi, kap, out=(R[:-1], K, kt)))
+    expect_arg_error(lambda: ctx.assemble(u, phi, kap, out=(R, K[:-1], kt)))
+    expect_arg_error(lambda: ctx.assemble(u, phi, kap, out=(R, K.float(), kt)))
+    expect_arg_error(lambda: ctx.assemble(u, phi, kap, out=(R, K, kt[:-1])))
+    expect_arg_error(lambda: ctx.assemble(u.float(), phi, kap, out=(R, K, kt)))
+
+
+def test_energy_jet_rejects_wrong_input_shape():
+    ctx = stub()
+    expect_arg_error(lambda: ctx.energy_jet(torch.zeros(7, 2, dtype=torch.float64)))
+    expect_arg_error(lambda: ctx.energy_jet(torch.zeros(21, dtype=torch.float64)))
+
+
+def test_adjoint_rejects_bad_reaction_dofs_and_targets():
+    ctx = stub()
+    u, phi, kap = fields(ctx)
+    bcs = [([0], [0.0])] * 2
+    bad = G.LoadPath(u, phi, kap, bcs, [ctx.ndof], [0.0, 0.0])
+    expect_arg_error(lambda: ctx.adjoint(bad))
+    short = G.LoadPath(u, phi, kap, bcs, [1], [0.0])
+    expect_arg_error(lambda: ctx.adjoint(short))

@@ -64,7 +64,7 @@ def path_bc(case, n):
 
 def path_increment(case, n):
     prev = LEVELS[n - 2] if n > 1 else 0.0
-    return W.uniaxial_predictor(case, np.zeros_like(case.u), n) * (LEVELS[n - 1] - prev)
+    return W.uniaxial_increment(case) * (LEVELS[n - 1] - prev)
 
 
 def oracle_path(case, theta_e=None, theta_y=None):

@@ -1,0 +1,140 @@
+"""The closed-form model of Sec. 4.1 on the GPU (compressible Neo-Hooke energy,
+G = identity yield, i.e. the Ostwald loading function) and the staggered
+scheme of Sec. 3.2, against the oracle:
+
+* residual, tangent and history of one assembly, 2-D and 3-D, at 1e-12;
+* staggered load steps (history held at kappa_n in the global solve, updated
+  once at the converged fields) on a notched plate with the network model;
+* the single-element study of Sec. 5.1 (local model, uniaxial tension of one
+  Hex8 element): kappa(stretch) does not depend on eta_d or kappa_d, and the
+  GPU path equals the oracle's."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fem, solve
+
+from gpu_common import rel_err, state, sync, to_scipy
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+ATOL = 1e-11
+
+
+def closed_variant(case, beta_d=1000.0, c_d=1.0):
+    mu, lam = W.lame(210.0, 0.3)
+    mat = dict(case.material, mu_e=mu, lambda_e=lam, beta_d=beta_d, c_d=c_d)
+    return dataclasses.replace(case, material=mat, energy=W.CLOSED_FORM, yield_=W.IDENTITY_YIELD,
+                               theta_e=np.zeros(0), theta_y=np.zeros(0))
+
+
+@pytest.mark.parametrize("cfg,kw", [(1, dict(n=8)), (2, dict(n=4, nz=2)), (3, dict(n=20))])
+def test_closed_form_assembly_matches_oracle(cfg, kw):
+    from paper_2604_03411_amd import gedmg as G
+    case = closed_variant(W.make_case(cfg, **kw))
+    u, phi, kap = state(case, 300 + cfg, amp=0.08)
+    kap = kap * 20.0  # spread the history over both sides of kappa_d and of the yield point
+    R0, K0, k0 = fem.assemble(fem.Model(case), case.mesh, fem.dof_vector(u, phi), kap)
+    ctx = G.Context.from_case(case)
+    R, K, kt = ctx.assemble(*ctx.fields(u, phi, kap), "fp64")
+    sync()
+    assert ctx.status() == 0
+    Kg = to_scipy(ctx, K)
+    eR, eK, ek = rel_err(R.cpu().numpy(), R0), rel_err(Kg.data, K0.data), rel_err(kt.cpu().numpy(), k0)
+    print(f"[closed-form assembly] cfg {cfg}: R {eR:.2e} K {eK:.2e} kappa {ek:.2e}; "
+          f"yielded {(k0 > kap).mean():.2f}", flush=True)
+    assert 0.0 < (k0 > kap).mean() < 1.0
+    assert eR <= TOL and eK <= TOL and ek <= TOL
+    # a low-precision request has no layer products to lower: identical results
+    R2, K2, k2 = ctx.assemble(*ctx.fields(u, phi, kap), "bf16")
+    sync()
+    assert torch.equal(R2, R) and torch.equal(K2, K) and torch.equal(k2, kt)
+    ctx.close()
+
+
+def test_adjoint_rejects_the_closed_form_model():
+    from paper_2604_03411_amd import gedmg as G
+    case = closed_variant(W.make_case(5, n=4))
+    case.n_steps = 2
+    ctx = G.Context.from_case(case)
+    bcs = [W.uniaxial_bc(case, n) for n in (1, 2)]
+    path = G.LoadPath(case.u, case.phi, case.kappa, bcs, W.reaction_dofs(case), [0.0, 0.0])
+    with pytest.raises(G.GedmgError) as e:
+        ctx.adjoint(path)
+    assert e.value.code == -2
+    ctx.close()
+
+
+def test_staggered_steps_match_oracle():
+    """The staggered scheme on the 16 x 16 notched plate (network model), 4 load
+    steps: GPU against the oracle's staggered Newton, states and reactions."""
+    from paper_2604_03411_amd import gedmg as G
+    from test_gpu_newton import run_gpu_path
+    case = W.make_case(3, n=16)
+    case.n_steps = 8
+    print("[staggered] notched plate q4 16x16, 4 steps", flush=True)
+    gpu = run_gpu_path(G, case, 4, W.uniaxial_bc, predictor_du=W.uniaxial_increment(case), scheme="staggered")
+    recs = solve.load_path(case, fem.Model(case), steps=4, rtol=0.0, atol=ATOL, scheme="staggered")
+    mono = solve.load_path(case, fem.Model(case), steps=4, rtol=0.0, atol=ATOL)
+    for (ug, pg, kg, rep), r, rm in zip(gpu, recs, mono):
+        uo, po = fem.split_dofs(r["d"], 2)
+        print(f"  step {r['step']}: reaction gpu {rep['reaction']:.10g} oracle {r['reaction']:.10g} "
+              f"(monolithic {rm['reaction']:.10g}); max kappa {kg.max():.4g} vs monolithic {rm['kappa'].max():.4g}",
+              flush=True)
+        assert abs(rep["reaction"] - r["reaction"]) <= 1e-8 * abs(r["reaction"])
+        assert rel_err(ug, uo) < 1e-8 and rel_err(pg, po) < 1e-6 and rel_err(kg, r["kappa"]) < 1e-6
+    # the lag of the staggered history (Sec. 3.2): less damage than the monolithic path
+    assert gpu[-1][2].max() < mono[-1]["kappa"].max()
+
+
+def _single_element_gpu(G, eta, kd, steps):
+    case = W.single_element_case(eta_d=eta, kappa_d=kd, n_steps=steps)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    du = W.uniaxial_increment(case)
+    out = []
+    for n in range(1, steps + 1):
+        bd, bv = W.symmetric_tension_bc(case, n)
+        rep = ctx.newton_step(u, phi, kap, bd, bv, reaction_dofs=W.reaction_dofs(case), predictor_du=du,
+                              scheme="staggered", newton_rtol=1e-12, newton_atol=0.0, newton_rscale=0.0,
+                              krylov_rtol=1e-14)
+        sync()
+        out.append((u.cpu().numpy().copy(), kap.cpu().numpy().copy(), rep))
+    ctx.close()
+    return case, out
+
+
+def test_single_element_study_kappa_independent_of_damage_parameters():
+    """Sec. 5.1: one Hex8 element under uniaxial tension to 0.5 mm, local
+    closed-form model; for (eta_d, kappa_d) over the paper's ranges, kappa at
+    every stretch is the same, equal to the oracle's, and d = 1 - f_d(kappa)
+    grows with eta_d and starts later with kappa_d."""
+    from paper_2604_03411_amd import gedmg as G
+    steps = 12
+    params = ((1.0, 0.0), (10.0, 0.0), (100.0, 0.0), (10.0, 1.0), (10.0, 2.0))
+    runs = {p: _single_element_gpu(G, *p, steps) for p in params}
+    k_ref = np.array([k for _, k, _ in runs[params[0]][1]])
+    for p, (case, out) in runs.items():
+        ks = np.array([k for _, k, _ in out])
+        assert np.allclose(ks, k_ref, rtol=1e-10, atol=1e-13), p
+    case, out = runs[(10.0, 1.0)]
+    du = W.uniaxial_increment(case)
+    recs = solve.load_path(case, fem.Model(case), bc_fn=W.symmetric_tension_bc,
+                           predictor_fn=lambda c, u, n: u + du, rtol=1e-12, atol=0.0, rscale=0.0,
+                           scheme="staggered")
+    for (ug, kg, rep), r in zip(out, recs):
+        uo, _ = fem.split_dofs(r["d"], 3)
+        assert rel_err(ug, uo) < 1e-10 and rel_err(kg, r["kappa"]) < 1e-10
+        assert abs(rep["reaction"] - r["reaction"]) <= 1e-8 * max(abs(r["reaction"]), 1e-300)
+    kk = k_ref[:, 0, 0]
+    print("[single element] kappa per step: " + " ".join(f"{v:.4g}" for v in kk), flush=True)
+    # d = 1 - f_d at a moderate stretch grows with eta_d ...
+    k4 = kk[3]
+    d4 = [1.0 - np.exp(-eta * k4) for eta in (1.0, 10.0, 100.0)]
+    assert d4[0] < d4[1] < d4[2]
+    # ... and its onset (the first step with kappa > kappa_d) comes later with kappa_d
+    onset = [int(np.argmax(kk > kd)) for kd in (0.0, 1.0, 2.0)]
+    assert onset[0] < onset[1] < onset[2]

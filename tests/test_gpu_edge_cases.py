@@ -75,9 +75,10 @@ def test_inverted_elements_report_status(G):
 
 
 def test_local_update_iteration_limit_is_reported(G):
-    """With max_local = 1 the FP64 local Newton cannot meet its 1e-15 test at
-    damaging points: the load step returns the local non-convergence code and
-    leaves the fields at their input values."""
+    """With max_local = 1 the FP64 local Newton cannot reach its acceptance test
+    (a correction below 1e-13 max(1, |kappa|), or a bracket narrower than 1e-15
+    max(1, |kappa|)) at damaging points: the load step returns the local
+    non-convergence code and leaves the fields at their input values."""
     case = W.make_case(2, n=4, nz=2)
     ctx = G.Context.from_case(case)
     u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
@@ -112,3 +113,26 @@ def test_invalid_arguments_are_rejected(G):
     with pytest.raises(G.GedmgError) as e:
         G.Context(case.mesh, case.material, wide, np.zeros(wide.n_params), case.yield_, case.theta_y)
     assert e.value.code == E_SHAPE
+
+
+def test_library_rejects_out_of_range_reaction_dofs(G):
+    """The C entry point checks reaction dofs itself (a caller of the C ABI has
+    no binding in front of it): GEDMG_E_ARG, fields untouched."""
+    import ctypes as C
+    case = W.make_case(1, n=2)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    u0 = u.clone()
+    dofs = torch.tensor([0], dtype=torch.int32, device=ctx.dev)
+    vals = torch.zeros(1, dtype=torch.float64, device=ctx.dev)
+    rd = torch.tensor([ctx.ndof], dtype=torch.int32, device=ctx.dev)
+    bc = G.Dirichlet(1, C.c_void_p(dofs.data_ptr()), C.c_void_p(vals.data_ptr()))
+    opts = G.solver_opts()
+    rep = G.NewtonReport()
+    rc = G.lib().gedmg_newton_step(ctx._h, C.byref(bc), C.byref(opts), 0, None, C.c_void_p(u.data_ptr()),
+                                   C.c_void_p(phi.data_ptr()), C.c_void_p(kap.data_ptr()),
+                                   C.c_void_p(rd.data_ptr()), 1, C.byref(rep))
+    sync()
+    assert rc == E_ARG
+    assert torch.equal(u, u0)
+    ctx.close()

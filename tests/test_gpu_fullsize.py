@@ -127,10 +127,11 @@ def _notched_path(G, case, precision):
     ctx = G.Context.from_case(case)
     u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
     out = []
+    du = W.uniaxial_increment(case)
     for n in range(1, case.n_steps + 1):
-        u.copy_(torch.as_tensor(W.uniaxial_predictor(case, u.cpu().numpy(), n), device=ctx.dev))
         bd, bv = W.uniaxial_bc(case, n)
-        rep = ctx.newton_step(u, phi, kap, bd, bv, precision, reaction_dofs=W.reaction_dofs(case))
+        rep = ctx.newton_step(u, phi, kap, bd, bv, precision, reaction_dofs=W.reaction_dofs(case),
+                              predictor_du=du)
         sync()
         if n % 10 == 0:
             print(f"  {precision} step {n}: iters {rep['newton_iters']} krylov {rep['krylov_iters']} "
@@ -180,15 +181,15 @@ def test_full_size_adjoint_directional_derivative():
     steps = case.n_steps
     print(f"[full-size adjoint] q4 128^2: {case.mesh.n_elems} elements, {steps} steps", flush=True)
     ctx = G.Context.from_case(case)
-    du = np.stack([W.uniaxial_predictor(case, np.zeros_like(case.u), n) for n in range(1, steps + 1)])
+    du = np.stack([W.uniaxial_increment(case)] * steps)
     bcs = [W.uniaxial_bc(case, n) for n in range(1, steps + 1)]
     rd = W.reaction_dofs(case)
     ctx.set_params(case.extra["theta_e_star"], case.extra["theta_y_star"])
     u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
     targets = []
     for n in range(1, steps + 1):
-        u += torch.as_tensor(du[n - 1], device=ctx.dev)
-        targets.append(ctx.newton_step(u, phi, kap, *bcs[n - 1], reaction_dofs=rd)["reaction"])
+        targets.append(ctx.newton_step(u, phi, kap, *bcs[n - 1], reaction_dofs=rd,
+                                       predictor_du=du[n - 1])["reaction"])
     ctx.set_params(case.theta_e, case.theta_y)
     path = G.LoadPath(case.u, case.phi, case.kappa, bcs, rd, targets, predictor_du=du)
     loss, ge, gy, _ = ctx.adjoint(path, checkpoint_every=5)

@@ -20,17 +20,21 @@ pytestmark = pytest.mark.gpu
 ATOL = 1e-11
 
 
-def run_gpu_path(G, case, steps, bc_fn, guess_fn, precision="fp64", krylov_forcing=True):
+def run_gpu_path(G, case, steps, bc_fn, guess_fn=None, precision="fp64", krylov_forcing=True,
+                 predictor_du=None, **solver):
+    """Load steps through gedmg_newton_step: either a seeded initial guess per
+    step (guess_fn(n) -> u, set before the call) or a predictor increment
+    (predictor_du, applied by the call itself)."""
     ctx = G.Context.from_case(case)
     u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
     out = []
     for n in range(1, steps + 1):
-        u0 = guess_fn(n, u.cpu().numpy())
-        u.copy_(torch.as_tensor(u0, device=ctx.dev))
+        if guess_fn is not None:
+            u.copy_(torch.as_tensor(guess_fn(n), device=ctx.dev))
         bd, bv = bc_fn(case, n)
         rep = ctx.newton_step(u, phi, kap, bd, bv, precision, reaction_dofs=W.reaction_dofs(case),
-                              newton_rtol=0.0, newton_atol=ATOL, krylov_rtol=1e-13,
-                              krylov_forcing=krylov_forcing)
+                              predictor_du=predictor_du, newton_rtol=0.0, newton_atol=ATOL, krylov_rtol=1e-13,
+                              krylov_forcing=krylov_forcing, **solver)
         sync()
         print(f"  gpu step {n}: iters {rep['newton_iters']} krylov {rep['krylov_iters']} "
               f"res {rep['res_norm'][-1]:.2e} reaction {rep['reaction']:.6g}", flush=True)
@@ -43,7 +47,7 @@ def test_uniform_stretch_steps_match_oracle_and_closed_form():
     from paper_2604_03411_amd import gedmg as G
     case = W.make_case(2, n=6, nz=3)
     print("[newton] uniform stretch hex8 6x6x3", flush=True)
-    gpu = run_gpu_path(G, case, 3, W.affine_stretch_bc, lambda n, u: W.affine_stretch_guess(case, n))
+    gpu = run_gpu_path(G, case, 3, W.affine_stretch_bc, lambda n: W.affine_stretch_guess(case, n))
     m = fem.Model(case)
     u, phi, kap = case.u, case.phi, case.kappa
     lam = case.extra["stretch"]
@@ -68,12 +72,7 @@ def test_notched_plate_steps_match_oracle():
     case = W.make_case(3, n=16)
     case.n_steps = 8
     print("[newton] notched plate q4 16x16, 4 steps", flush=True)
-    state = {"u": case.u.copy()}
-
-    def guess(n, u_prev):
-        return W.uniaxial_predictor(case, u_prev, n)
-
-    gpu = run_gpu_path(G, case, 4, W.uniaxial_bc, guess)
+    gpu = run_gpu_path(G, case, 4, W.uniaxial_bc, predictor_du=W.uniaxial_increment(case))
     recs = solve.load_path(case, fem.Model(case), steps=4, rtol=0.0, atol=ATOL)
     for (ug, pg, kg, rep), r in zip(gpu, recs):
         uo, po = fem.split_dofs(r["d"], 2)
@@ -90,12 +89,10 @@ def test_inexact_and_exact_linear_solves_reach_the_same_states():
     case = W.make_case(3, n=16)
     case.n_steps = 8
 
-    def guess(n, u_prev):
-        return W.uniaxial_predictor(case, u_prev, n)
-
+    du = W.uniaxial_increment(case)
     print("[newton] notched plate q4 16x16, 4 steps, inexact vs exact solves", flush=True)
-    exact = run_gpu_path(G, case, 4, W.uniaxial_bc, guess, krylov_forcing=False)
-    inexact = run_gpu_path(G, case, 4, W.uniaxial_bc, guess, krylov_forcing=True)
+    exact = run_gpu_path(G, case, 4, W.uniaxial_bc, krylov_forcing=False, predictor_du=du)
+    inexact = run_gpu_path(G, case, 4, W.uniaxial_bc, krylov_forcing=True, predictor_du=du)
     for (u0, p0, k0, r0), (u1, p1, k1, r1) in zip(exact, inexact):
         assert r1["res_norm"][-1] <= ATOL and r0["res_norm"][-1] <= ATOL
         assert rel_err(u1, u0) < 1e-8 and rel_err(p1, p0) < 1e-6 and rel_err(k1, k0) < 1e-6
