@@ -201,6 +201,23 @@ int gedmg_csr(gedmg_ctx* ctx, int64_t* n_rows, int64_t* nnz, const int32_t** row
 int gedmg_assemble(gedmg_ctx* ctx, const double* u, const double* phi, const double* kappa_n,
                    int precision, double* R, double* K_vals, double* kappa_trial);
 
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * gedmg_assemble with the per-point scratch of the assembly (network inputs,
+ * jets, phi at the points, history sensitivities) in a static device array of
+ * the library instead of buffers of the context.  Arguments, outputs and
+ * errors are those of gedmg_assemble; the results are bitwise identical to it.
+ * The call allocates nothing (no hipMalloc / hipFree, no events), clears R
+ * with a kernel rather than a memset node, and rejects meshes with more than
+ * GEDMG_STATIC_MAX_QP quadrature points (n_elems * nqp) with GEDMG_E_ARG.  The
+ * array (GEDMG_STATIC_MAX_QP x 16 doubles = 32 MiB) exists once per GPU and
+ * lives until the process ends; it is shared by every context on that GPU and
+ * keeps the last call's contents, so calls that overlap on one GPU (two
+ * streams, two host threads) race and must be serialised by the caller. */
+#define GEDMG_STATIC_MAX_QP 262144
+int gedmg_assemble_static(gedmg_ctx* ctx, const double* u, const double* phi, const double* kappa_n,
+                          int precision, double* R, double* K_vals, double* kappa_trial);
+
 /* Diagnostic: the energy-network jet at given inputs, in the arithmetic
  * selected by precision (used by the tests and by the mixed-precision error
  * report).  x: device [n][3] inputs (I1G - 3, I2G - 3, J - 1); jet: device

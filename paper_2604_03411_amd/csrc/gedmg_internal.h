@@ -167,6 +167,10 @@ Material element_material(const gedmg_ctx* c);
 int assemble_impl(gedmg_ctx* c, const double* u, const double* phi, const double* kappa_n, int precision,
                   double* R, double* K_vals, double* kappa_trial, const AssembleScratch& sc, bool fill_kernel);
 
+// Device address of the static scratch array on `device` (set up by gedmg_create).
+int static_scratch_init(int device, std::string& err);
+double* static_scratch_ptr(int device);
+
 // Defaults of gedmg_solver_opts (used when a caller passes NULL).
 gedmg_solver_opts default_solver_opts();
 

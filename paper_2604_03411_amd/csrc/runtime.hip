@@ -320,6 +320,7 @@ int gedmg_create(gedmg_ctx** out, const gedmg_mesh* mesh, const gedmg_material* 
   if (rc) return fail(rc);
   c->stream = (hipStream_t)hip_stream;
   GEDMG_HIP(c, hipGetDevice(&c->device));
+  if ((rc = static_scratch_init(c->device, c->err))) return fail(rc);
   GEDMG_HIP(c, hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device));
   c->dim = mesh->dim;
   c->nen = c->dim == 3 ? 8 : 4;

@@ -112,6 +112,8 @@ def lib():
         L.gedmg_set_params.argtypes = [vp, C.POINTER(dp), C.POINTER(dp)]
         L.gedmg_csr.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(vp), C.POINTER(vp)]
         L.gedmg_assemble.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp, vp]
+        if hasattr(L, "gedmg_assemble_static"):
+            L.gedmg_assemble_static.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L.gedmg_status.argtypes = [vp]
         L.gedmg_energy_jet.argtypes = [vp, vp, i64, C.c_int, vp]
         L.gedmg_profile.argtypes = [vp, C.c_int]
@@ -126,7 +128,7 @@ def lib():
                                         C.POINTER(SolverOpts), vp, vp, vp, C.POINTER(dp), C.POINTER(dp),
                                         C.POINTER(dp), C.POINTER(AdjointReport)]
         for name in ("gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
-                     "gedmg_assemble", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
+                     "gedmg_assemble", "gedmg_assemble_static", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
                      "gedmg_energy_jet", "gedmg_profile", "gedmg_profile_read", "gedmg_probe_mfma"):
             if hasattr(L, name):
                 getattr(L, name).restype = C.c_int
@@ -134,8 +136,10 @@ def lib():
     return _lib
 
 
+STATIC_MAX_QP = 262144  # GEDMG_STATIC_MAX_QP
+
 EXPORTED = ("gedmg_last_error", "gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
-            "gedmg_assemble", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
+            "gedmg_assemble", "gedmg_assemble_static", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
             "gedmg_energy_jet", "gedmg_profile", "gedmg_profile_read", "gedmg_probe_mfma")
 
 
@@ -278,8 +282,10 @@ class Context:
         _check_array(phi, self.n_nodes, self.dev, "phi")
         _check_array(kappa, self.n_elems * self.nqp, self.dev, "kappa")
 
-    def assemble(self, u, phi, kappa, precision="fp64", tangent=True, out=None):
-        """Returns (R [ndof], K_vals [nnz] or None, kappa_trial [n_elems, nqp]) on the device."""
+    def assemble(self, u, phi, kappa, precision="fp64", tangent=True, out=None, static_scratch=False):
+        """Returns (R [ndof], K_vals [nnz] or None, kappa_trial [n_elems, nqp]) on the device.
+        static_scratch: call gedmg_assemble_static (no allocation inside the
+        library; pass `out` to allocate nothing on the Python side either)."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         if out is None:
             R = torch.empty(self.ndof, dtype=torch.float64, device=self.dev)
@@ -294,8 +300,8 @@ class Context:
                     raise GedmgError(-1, "K_vals must be 16-byte aligned")
             _check_array(kt, self.n_elems * self.nqp, self.dev, "kappa_trial")
         self._check_fields(u, phi, kappa)
-        self._check(lib().gedmg_assemble(self._h, _dptr(u), _dptr(phi), _dptr(kappa), prec, _dptr(R), _dptr(K),
-                                         _dptr(kt)))
+        fn = lib().gedmg_assemble_static if static_scratch else lib().gedmg_assemble
+        self._check(fn(self._h, _dptr(u), _dptr(phi), _dptr(kappa), prec, _dptr(R), _dptr(K), _dptr(kt)))
         return R, K, kt
 
     def energy_jet(self, x, precision="fp64"):
