@@ -136,6 +136,11 @@ typedef struct {
    * are tested absolutely); 0 makes the test purely relative to ||R_f^0||, for
    * states whose whole residual is scaled by a tiny degradation f_d. */
   double newton_rscale;
+  /* Krylov method of the Newton solves: 0 (default) CG with the Jacobi + coarse
+   * preconditioner, switching to BiCGStab when it meets non-positive curvature;
+   * 1 BiCGStab with Jacobi from the start, for tangents that are not symmetric
+   * (gamma_d != 1, or history in the window kappa_n < kappa <= kappa_d). */
+  int32_t krylov_method;
 } gedmg_solver_opts;
 
 enum { GEDMG_MONOLITHIC = 0, GEDMG_STAGGERED = 1 };
@@ -147,6 +152,10 @@ typedef struct {
   int32_t status;             /* same code as the return value */
   double res_norm[32];        /* ||R_f|| per Newton iteration (first 32) */
   double reaction;            /* sum of R over the reaction dofs given to newton_step, 0 if none */
+  int32_t backtracks;         /* halvings of Newton corrections that inverted an element or gave a
+                                 non-finite residual (at most 12 per load step) */
+  int32_t krylov_fallbacks;   /* linear solves in which CG met non-positive curvature and BiCGStab
+                                 took over */
 } gedmg_newton_report;
 
 typedef struct {
@@ -259,7 +268,8 @@ int gedmg_status(gedmg_ctx* ctx);
  *   3. runs Newton on the free dofs, with a preconditioned Krylov solve of
  *      K_ff d = -R_f per iteration (CG with Jacobi plus a coarse correction on
  *      the uniform damage field; BiCGStab with Jacobi when CG meets
- *      non-positive curvature on a non-symmetric or indefinite tangent), until
+ *      non-positive curvature on a non-symmetric or indefinite tangent), a
+ *      correction that inverts an element being halved (up to 12 times), until
  *      ||R_f|| <= max(newton_rtol max(newton_rscale, ||R_f^0||), newton_atol);
  *   4. commits kappa_{n+1} (staggered: the local update of Eq. dd_7 at the
  *      converged fields, computed once after the global solve with kappa_n).

@@ -130,9 +130,15 @@ __device__ __forceinline__ double log1p_small(double y) {
 // occur in deep networks with large weights), sb0 underflows and the a > 0
 // form returns d + log(s0) exactly, where the a <= 0 form alone would saturate.
 
-// ---- table-driven variants; the caller stages the kMathTabDoubles-entry table
-// (exp: 64 x (Thi, Tlo); log: 64 x (1/c, log c hi, log c lo, 0); built on the
-// host by build_math_tables) in LDS.
+// ---- table-driven variants, after the published methods of P. T. P. Tang
+// ("Table-driven implementation of the exponential function in IEEE
+// floating-point arithmetic", ACM TOMS 15(2), 1989, and "Table-driven
+// implementation of the logarithm function in IEEE floating-point arithmetic",
+// ACM TOMS 16(4), 1990): argument reduction against a table of 2^(j/64)
+// (exponential) or of reciprocals of interval centres (logarithm), then a short
+// polynomial.  The caller stages the kMathTabDoubles-entry table (exp: 64 x
+// (Thi, Tlo); log: 64 x (1/c, log c hi, log c lo, 0); built on the host by
+// build_math_tables) in LDS.
 // exp / expm1: t = (64 n + j) ln2/64 + r with |r| <= ln2/128 (ln2/64 split so
 // that the products with the integer multiple are exact), 2^(j/64) = Thi + Tlo
 // from the table, expm1(r) by its Taylor series through r^6 (truncation below

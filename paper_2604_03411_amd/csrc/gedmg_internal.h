@@ -163,9 +163,13 @@ Material element_material(const gedmg_ctx* c);
 
 // One assembly (gedmg_assemble) with the given scratch.  fill_kernel: clear R
 // with a kernel instead of hipMemsetAsync and record no profiling events (the
-// form that a caller may capture in a graph).
+// form that a caller may capture in a graph).  refine64 (low precision only):
+// the network value and gradient are recomputed in FP64, so R and the history
+// are those of the FP64 path and only the tangent carries the low-precision
+// Hessian (one pass per iteration of the mixed-precision Newton step).
 int assemble_impl(gedmg_ctx* c, const double* u, const double* phi, const double* kappa_n, int precision,
-                  double* R, double* K_vals, double* kappa_trial, const AssembleScratch& sc, bool fill_kernel);
+                  double* R, double* K_vals, double* kappa_trial, const AssembleScratch& sc, bool fill_kernel,
+                  bool refine64);
 
 // Device address of the static scratch array on `device` (set up by gedmg_create).
 int static_scratch_init(int device, std::string& err);

@@ -49,7 +49,11 @@ struct JetCfg {
   static_assert(L <= 3, "the middle-layer Jacobian is recovered from the last activation buffer");
 };
 
-template <int H, int L>
+// HESS = false: value and gradient only, in reverse mode (1 forward column,
+// the activation increment, and 1 adjoint column per layer; the gradient is
+// the input weights contracted with the adjoints), writing jet entries 0..3
+// and leaving the Hessian entries as they are.
+template <int H, int L, bool HESS>
 __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
   using C = JetCfg<H, L>;
   constexpr int NT = C::NT, QB = C::QB, QP = C::QP, NS = H / 4;
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
 #pragma unroll
     for (int t = 0; t < 10; ++t) part[t] = 0.0;
     double abar[4];
-    const bool hess = a.with_hessian != 0;
+    constexpr bool hess = HESS;
 
     // layer 1: a_1 = W0 x + b0 (vector ALU)
 #pragma unroll
@@ -120,15 +124,23 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
       const double w0 = c0[3 * H], w1 = c0[4 * H], w2 = c0[5 * H];
       const double da = w0 * x[0] + w1 * x[1] + w2 * x[2];
       dz[r] = delta_softplus_tab(da, c0[0], c0[H], c0[2 * H], s0r[r], sb0r[r], et, lt);
-      zt[r][0] = s0r[r] * w0;
-      zt[r][1] = s0r[r] * w1;
-      zt[r][2] = s0r[r] * w2;
+      if (HESS) {
+        zt[r][0] = s0r[r] * w0;
+        zt[r][1] = s0r[r] * w1;
+        zt[r][2] = s0r[r] * w2;
+      }
       if (L == 1) {
         const double wz = cst[L * 6 * H + n];
         part[0] += wz * dz[r];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
         abar[r] = wz * s0r[r];
+        if (HESS) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
+        } else {
+          part[1] += abar[r] * w0;
+          part[2] += abar[r] * w1;
+          part[3] += abar[r] * w2;
+        }
         if (hess) {
           const double c2 = abar[r] * sb0r[r];
           part[4] += c2 * w0 * w0;
@@ -143,12 +155,15 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
 
 #pragma unroll
     for (int k = 1; k < L; ++k) {
+      constexpr int NCOL = HESS ? 4 : 1;  // forward columns
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int n = nt * 16 + lg + 4 * r;
         Zs[n * QP + j] = dz[r];
+        if (HESS) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) Zs[(1 + i) * H * QP + n * QP + j] = zt[r][i];
+          for (int i = 0; i < 3; ++i) Zs[(1 + i) * H * QP + n * QP + j] = zt[r][i];
+        }
       }
       __syncthreads();
       d4_t acc[4];
@@ -160,7 +175,7 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
         const double av = Wk[s * 64];
         const int zb = (4 * s + lg) * QP + li;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < NCOL; ++c)
           acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Zs[c * H * QP + zb], acc[c], 0, 0, 0);
       }
       __syncthreads();
@@ -172,18 +187,27 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
         const double wx[3] = {ck[3 * H], ck[4 * H], ck[5 * H]};
         const double da = acc[0][r] + wx[0] * x[0] + wx[1] * x[1] + wx[2] * x[2];
         double jk[3];
+        if (HESS) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) jk[i] = acc[1 + i][r] + wx[i];
+          for (int i = 0; i < 3; ++i) jk[i] = acc[1 + i][r] + wx[i];
+        }
         double s_, sb_;
         dz[r] = delta_softplus_tab(da, ck[0], ck[H], ck[2 * H], s_, sb_, et, lt);
+        if (HESS) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) zt[r][i] = s_ * jk[i];
+          for (int i = 0; i < 3; ++i) zt[r][i] = s_ * jk[i];
+        }
         if (k == L - 1) {
           const double wz = cst[L * 6 * H + n];
           part[0] += wz * dz[r];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
           abar[r] = wz * s_;
+          if (HESS) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) part[1 + i] += wz * zt[r][i];
+          } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) part[1 + i] += abar[r] * wx[i];
+          }
           if (hess) {
             const double c2 = abar[r] * sb_;
             part[4] += c2 * jk[0] * jk[0];
@@ -193,9 +217,36 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
             part[8] += c2 * jk[0] * jk[2];
             part[9] += c2 * jk[1] * jk[2];
           }
-        } else if (hess) {
+        } else {
           stk[(0 * 4 + r) * 64] = s_;
-          stk[(1 * 4 + r) * 64] = sb_;
+          if (HESS) stk[(1 * 4 + r) * 64] = sb_;
+        }
+      }
+    }
+
+    if (!HESS) {
+      // reverse sweep for the gradient: zbar_{k-1} = W_k^T abar_k,
+      // abar_{k-1} = s_{k-1} zbar_{k-1}, grad += W_x,{k-1}^T abar_{k-1}
+#pragma unroll
+      for (int k = L - 1; k >= 1; --k) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Zs[(nt * 16 + lg + 4 * r) * QP + j] = abar[r];
+        __syncthreads();
+        d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+        const double* Wt = wop + ((size_t)((k - 1) * 2 + 1) * NT + nt) * NS * 64 + lane;
+#pragma unroll 8
+        for (int s = 0; s < NS; ++s)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wt[s * 64], Zs[(4 * s + lg) * QP + li], acc, 0, 0, 0);
+        __syncthreads();
+        const double* stk = st + ((size_t)(k - 2) * NT + nt) * 2 * 4 * 64 + lane;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int n = nt * 16 + lg + 4 * r;
+          const double sv = (k - 1 == 0) ? s0r[r] : stk[(0 * 4 + r) * 64];
+          abar[r] = acc[r] * sv;
+          const double* wcol = cst + (k - 1) * 6 * H + n;  // input weights of layer k-1
+#pragma unroll
+          for (int i = 0; i < 3; ++i) part[1 + i] += abar[r] * wcol[(3 + i) * H];
         }
       }
     }
@@ -258,8 +309,9 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
       for (int t = 0; t < 10; ++t) red[(nt * QB + j) * 10 + t] = part[t];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < QB * 10; idx += blockDim.x) {
-      const int jj = idx / 10, t = idx % 10;
+    constexpr int NOUT = HESS ? 10 : 4;
+    for (int idx = threadIdx.x; idx < QB * NOUT; idx += blockDim.x) {
+      const int jj = idx / NOUT, t = idx % NOUT;
       double v = 0.0;
 #pragma unroll
       for (int u = 0; u < NT; ++u) v += red[(u * QB + jj) * 10 + t];
@@ -271,20 +323,25 @@ __global__ __launch_bounds__(H * 4, 2) void jet_f64_kernel(JetArgs a) {
   }
 }
 
-template <int H, int L>
-static hipError_t launch_f64(const JetArgs& a, hipStream_t s, int num_cu) {
+template <int H, int L, bool HESS>
+static hipError_t launch_f64_mode(const JetArgs& a, hipStream_t s, int num_cu) {
   using C = JetCfg<H, L>;
   const int nbatch = (a.nq + C::QB - 1) / C::QB;
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jet_f64_kernel<H, L>, C::WAVES * 64,
-                                                              C::LDS_BYTES);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jet_f64_kernel<H, L, HESS>,
+                                                              C::WAVES * 64, C::LDS_BYTES);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   int grid = num_cu * per_cu;
   if (grid > nbatch) grid = nbatch;
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((jet_f64_kernel<H, L>), dim3(grid), dim3(C::WAVES * 64), C::LDS_BYTES, s, a);
+  hipLaunchKernelGGL((jet_f64_kernel<H, L, HESS>), dim3(grid), dim3(C::WAVES * 64), C::LDS_BYTES, s, a);
   return hipGetLastError();
+}
+
+template <int H, int L>
+static hipError_t launch_f64(const JetArgs& a, hipStream_t s, int num_cu) {
+  return a.with_hessian ? launch_f64_mode<H, L, true>(a, s, num_cu) : launch_f64_mode<H, L, false>(a, s, num_cu);
 }
 
 hipError_t launch_energy_jet_f64(int H, const JetArgs& a, hipStream_t s, int num_cu) {

@@ -234,7 +234,8 @@ Material element_material(const gedmg_ctx* c) {
 }
 
 int assemble_impl(gedmg_ctx* c, const double* u, const double* phi, const double* kappa_n, int precision,
-                  double* R, double* K_vals, double* kappa_trial, const AssembleScratch& sc, bool fill_kernel) {
+                  double* R, double* K_vals, double* kappa_trial, const AssembleScratch& sc, bool fill_kernel,
+                  bool refine64) {
   if (!u || !phi || !kappa_n || !R || !kappa_trial) { c->err = "null array argument"; return GEDMG_E_ARG; }
   if (precision != GEDMG_FP64 && precision != GEDMG_BF16 && precision != GEDMG_FP16) {
     c->err = "unknown precision";
@@ -270,6 +271,14 @@ int assemble_impl(gedmg_ctx* c, const double* u, const double* phi, const double
   JetArgs ja{sc.x, sc.jet, c->denet, precision == GEDMG_FP16 ? c->dw_f16 : c->dw_bf16, c->dwop,
              (int)nq, c->elay.L, K_vals ? 1 : 0, c->dmtab, c->mat.mu, c->mat.lam};
   GEDMG_HIP(c, launch_energy_jet(precision, c->elay.H, ja, c->stream, c->num_cu));
+  if (refine64 && precision != GEDMG_FP64 && c->elay.L > 0) {
+    // FP64 value and gradient over the low-precision ones (reverse mode, the
+    // Hessian entries stay those of the low-precision jet): the residual and the
+    // history are then those of the FP64 path, the tangent is the mixed one
+    JetArgs jr = ja;
+    jr.with_hessian = 0;
+    GEDMG_HIP(c, launch_energy_jet(GEDMG_FP64, c->elay.H, jr, c->stream, c->num_cu));
+  }
   if (prof) GEDMG_HIP(c, hipEventRecord(ev[3], c->stream));
   const Material em = element_material(c);
   HistArgs ha{sc.x, sc.jet, sc.phiq, kappa_n, c->dynet, kappa_trial, sc.sens, c->dstatus, (long)nq,
@@ -510,7 +519,7 @@ int gedmg_assemble(gedmg_ctx* c, const double* u, const double* phi, const doubl
                    int precision, double* R, double* K_vals, double* kappa_trial) {
   if (!c) return GEDMG_E_ARG;
   const AssembleScratch sc{c->dx, c->djet, c->dphiq, c->dsens};
-  return assemble_impl(c, u, phi, kappa_n, precision, R, K_vals, kappa_trial, sc, false);
+  return assemble_impl(c, u, phi, kappa_n, precision, R, K_vals, kappa_trial, sc, false, false);
 }
 
 static void prof_clear(gedmg_ctx* c) {

@@ -11,6 +11,8 @@
 // Sparse kernels are deterministic: fixed grids, per-block partial sums in a
 // fixed order, one-block final reductions; Krylov scalars stay on the device
 // and the host polls the residual norm only every few iterations.
+#include <hip/hip_cooperative_groups.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -21,6 +23,7 @@
 namespace gedmg {
 
 constexpr int kRedBlocks = 512;  // blocks of every reduction kernel
+constexpr int kMaxBacktracks = 12;  // halvings of one Newton correction
 constexpr int kThreads = 256;
 
 gedmg_solver_opts default_solver_opts() {
@@ -36,6 +39,7 @@ gedmg_solver_opts default_solver_opts() {
   o.refine_rtol = 1e-8;
   o.scheme = GEDMG_MONOLITHIC;
   o.newton_rscale = 1.0;
+  o.krylov_method = 0;
   return o;
 }
 
@@ -87,6 +91,20 @@ __global__ void update_fields_kernel(double* u, double* phi, const double* delta
     u[(long)c * n_nodes + node] += delta[i];
   else
     phi[node] += delta[i];
+}
+
+// Halve the last Newton correction: x holds it on entry and half of it on
+// exit, and the fields lose that half.
+__global__ void backtrack_kernel(double* u, double* phi, double* x, int dim, int n_nodes) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_nodes * (dim + 1)) return;
+  const double d = 0.5 * x[i];
+  x[i] = d;
+  const int node = (int)(i / (dim + 1)), c = (int)(i % (dim + 1));
+  if (c < dim)
+    u[(long)c * n_nodes + node] -= d;
+  else
+    phi[node] -= d;
 }
 
 __global__ void set_mask_kernel(const int32_t* dof, int n, long ndof, uint8_t* mask, double* scal) {
@@ -317,6 +335,199 @@ __global__ void cg_p_kernel(double* p, const double* r, const double* dinv, cons
   }
 }
 
+// ---- CG in one cooperative launch.  The whole preconditioned CG runs in one
+// kernel whose blocks are all resident (cooperative launch) and meet at grid
+// barriers, two per iteration, instead of three dependent launches per
+// iteration: on systems of tens of thousands of dofs the iteration is bound
+// by launch latency, not by the sparse product.
+//   phase A: from the partial sums of the last update, every block forms
+//            cc = (chi.r)/E, (r.z) = r.D^-1.r + cc (chi.r), beta and the
+//            convergence test; the search direction p_new = z + beta p_old,
+//            z = D^-1 r + cc chi, is formed on the fly for every column the
+//            product reads (rows write their own entry into the other p
+//            buffer), q = K p_new and partial sums of p_new.q;
+//   phase B: alpha = (r.z)/(p.q) from those partials; x += alpha p_new,
+//            r -= alpha q, partial sums of r.D^-1.r, r.r and chi.r.
+// Every block sums the partials in the same order, so the scalars and the
+// exit decisions (converged, non-positive curvature, non-finite, iteration
+// limit) are identical in every block and all blocks leave the loop together.
+namespace cgk = cooperative_groups;
+
+struct CoopCgArgs {
+  const double* K;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* b;       // right-hand side (prescribed rows zero)
+  const double* dinv;
+  const uint8_t* mask;
+  double* x;
+  double* r;
+  double* p0;
+  double* p1;
+  double* q;
+  double* part;          // [5][gridDim.x] partial sums
+  double* scal;          // out: iterations, status (0 converged, 1 curvature, 2 limit, 3 non-finite), r.r
+  long n;
+  int nd;
+  int max_it;
+  double tol2_rel;       // converged when r.r <= tol2_rel * b.b
+};
+
+__device__ __forceinline__ void block_sums3(const double* part, int nb, double* sh, double* bc, double& t1,
+                                            double& t2, double& t3) {
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    s1 += part[i];
+    s2 += part[nb + i];
+    s3 += part[2 * nb + i];
+  }
+  const double a1 = block_sum(s1, sh);
+  const double a2 = block_sum(s2, sh);
+  const double a3 = block_sum(s3, sh);
+  if (threadIdx.x == 0) {
+    bc[0] = a1;
+    bc[1] = a2;
+    bc[2] = a3;
+  }
+  __syncthreads();
+  t1 = bc[0];
+  t2 = bc[1];
+  t3 = bc[2];
+  __syncthreads();
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void cg_coop_kernel(CoopCgArgs a) {
+  __shared__ double sh[8];
+  __shared__ double bc[3];
+  cgk::grid_group grid = cgk::this_grid();
+  const int nb = gridDim.x;
+  const long n = a.n;
+  const int nd = a.nd;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x, nthr = (long)nb * blockDim.x;
+  double* ps = a.part;            // [3][nb]: r.D^-1.r, r.r, chi.r
+  double* pq_part = a.part + 3 * (long)nb;
+  double* pe_part = a.part + 4 * (long)nb;
+  // ---- x = 0, r = b; partials of chi.K.chi and of the three sums of r
+  {
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0, e = 0.0;
+    for (long i = tid; i < n; i += nthr) {
+      const double ri = a.b[i];
+      a.x[i] = 0.0;
+      a.r[i] = ri;
+      s1 += ri * a.dinv[i] * ri;
+      s2 += ri * ri;
+      if (chi(i, nd, a.mask)) {
+        s3 += ri;
+        for (int j = a.rowptr[i]; j < a.rowptr[i + 1]; ++j)
+          if (chi(a.col[j], nd, a.mask)) e += a.K[j];
+      }
+    }
+    double t = block_sum(s1, sh);
+    if (threadIdx.x == 0) ps[blockIdx.x] = t;
+    t = block_sum(s2, sh);
+    if (threadIdx.x == 0) ps[nb + blockIdx.x] = t;
+    t = block_sum(s3, sh);
+    if (threadIdx.x == 0) ps[2 * nb + blockIdx.x] = t;
+    t = block_sum(e, sh);
+    if (threadIdx.x == 0) pe_part[blockIdx.x] = t;
+  }
+  __threadfence();
+  grid.sync();
+  double E, bb;
+  {
+    double t1, t2, t3;
+    block_sums3(ps, nb, sh, bc, t1, bb, t3);
+    double se = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) se += pe_part[i];
+    const double te = block_sum(se, sh);
+    if (threadIdx.x == 0) bc[0] = te;
+    __syncthreads();
+    E = bc[0];
+    __syncthreads();
+  }
+  const double tol2 = a.tol2_rel * bb;
+  double rz_old = 0.0;
+  int status = 2, it = 0;
+  double rr = bb;
+  const int lane = threadIdx.x % G;
+  const long groups = (long)nb * (blockDim.x / G);
+  for (;; ++it) {
+    // ---- phase A
+    double S1, S2, S3;
+    block_sums3(ps, nb, sh, bc, S1, S2, S3);
+    rr = S2;
+    if (!(S2 == S2) || S2 > 1e300) { status = 3; break; }
+    if (S2 <= tol2) { status = 0; break; }
+    if (it >= a.max_it) { status = 2; break; }
+    const double cc = (E > 0.0) ? S3 / E : 0.0;
+    const double rz_new = S1 + cc * S3;
+    const bool first = it == 0;
+    const double beta = (!first && rz_old != 0.0) ? rz_new / rz_old : 0.0;
+    const double* pold = (it & 1) ? a.p1 : a.p0;
+    double* pnew = (it & 1) ? a.p0 : a.p1;
+    double acc = 0.0;
+    for (long row = (long)blockIdx.x * (blockDim.x / G) + threadIdx.x / G; row < n; row += groups) {
+      double sacc = 0.0;
+      for (int j = a.rowptr[row] + lane; j < a.rowptr[row + 1]; j += G) {
+        const int c = a.col[j];
+        const double z = a.dinv[c] * a.r[c] + (chi(c, nd, a.mask) ? cc : 0.0);
+        const double pc = first ? z : fma(beta, pold[c], z);
+        sacc = fma(a.K[j], pc, sacc);
+      }
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, G);
+      if (lane == 0) {
+        const double z = a.dinv[row] * a.r[row] + (chi(row, nd, a.mask) ? cc : 0.0);
+        const double pr = first ? z : fma(beta, pold[row], z);
+        pnew[row] = pr;
+        a.q[row] = sacc;
+        acc = fma(pr, sacc, acc);
+      }
+    }
+    {
+      const double t = block_sum(acc, sh);
+      if (threadIdx.x == 0) pq_part[blockIdx.x] = t;
+    }
+    rz_old = rz_new;
+    __threadfence();
+    grid.sync();
+    // ---- phase B
+    double spq = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) spq += pq_part[i];
+    const double tpq = block_sum(spq, sh);
+    if (threadIdx.x == 0) bc[0] = tpq;
+    __syncthreads();
+    const double pq = bc[0];
+    __syncthreads();
+    if (!(pq > 0.0)) { status = 1; break; }
+    const double alpha = rz_new / pq;
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (long i = tid; i < n; i += nthr) {
+      a.x[i] = fma(alpha, pnew[i], a.x[i]);
+      const double ri = fma(-alpha, a.q[i], a.r[i]);
+      a.r[i] = ri;
+      s1 += ri * a.dinv[i] * ri;
+      s2 += ri * ri;
+      if (chi(i, nd, a.mask)) s3 += ri;
+    }
+    double t = block_sum(s1, sh);
+    if (threadIdx.x == 0) ps[blockIdx.x] = t;
+    t = block_sum(s2, sh);
+    if (threadIdx.x == 0) ps[nb + blockIdx.x] = t;
+    t = block_sum(s3, sh);
+    if (threadIdx.x == 0) ps[2 * nb + blockIdx.x] = t;
+    __threadfence();
+    grid.sync();
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scal[0] = (double)it;
+    a.scal[1] = (double)status;
+    a.scal[2] = rr;
+    a.scal[3] = bb;
+  }
+}
+
 __global__ void precond_kernel(double* z, const double* r, const double* dinv, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     z[i] = dinv[i] * r[i];
@@ -413,8 +624,17 @@ struct Work {
   double *v = nullptr, *t = nullptr, *r0 = nullptr, *dinv = nullptr;
   double *ub = nullptr, *phib = nullptr;
   double *part = nullptr, *scal = nullptr, *hscal = nullptr;
+  double *cpart = nullptr, *cscal = nullptr;  // cooperative CG: partial sums, results
+  double* p1 = nullptr;                       // second search-direction buffer (cooperative CG)
   uint8_t* mask = nullptr;
+  int coop_blocks = 0;                        // grid of the cooperative CG (0: not sized yet)
 };
+
+constexpr int kCoopMaxBlocks = 4096;
+// Systems from this many dofs on are solved with the three-launch CG: there the
+// sparse product sets the pace and the cooperative grid (one to four blocks per
+// compute unit) has too few loads in flight for it.
+constexpr long kCoopMaxDofs = 1L << 18;
 
 }  // namespace
 
@@ -437,7 +657,8 @@ void release_newton_work(gedmg_ctx* c) {
     if (h[i]->ctx == c) {
       Work& w = h[i]->w;
       void* ptrs[] = {w.K, w.Kmp, w.R, w.Rmp, w.kt, w.ktmp, w.b, w.x, w.r, w.z, w.p, w.q,
-                      w.v, w.t, w.r0, w.dinv, w.ub, w.phib, w.part, w.scal, w.mask};
+                      w.v, w.t, w.r0, w.dinv, w.ub, w.phib, w.part, w.scal, w.mask,
+                      w.cpart, w.cscal, w.p1};
       for (void* p : ptrs)
         if (p) (void)hipFree(p);
       if (w.hscal) (void)hipHostFree(w.hscal);
@@ -468,7 +689,8 @@ int ensure_work(gedmg_ctx* c, Work** out) {
       al(&w.z, w.ndof) || al(&w.p, w.ndof) || al(&w.q, w.ndof) || al(&w.v, w.ndof) ||
       al(&w.t, w.ndof) || al(&w.r0, w.ndof) || al(&w.dinv, w.ndof) ||
       al(&w.ub, (long)c->dim * c->n_nodes) || al(&w.phib, c->n_nodes) ||
-      al(&w.part, 4 * kRedBlocks) || al(&w.scal, S_NSLOTS) ||
+      al(&w.part, 4 * kRedBlocks) || al(&w.scal, S_NSLOTS) || al(&w.cpart, 5L * kCoopMaxBlocks) ||
+      al(&w.cscal, 4) || al(&w.p1, w.ndof) ||
       hipMalloc((void**)&w.mask, std::max(w.ndof, 1L)) ||
       hipHostMalloc((void**)&w.hscal, sizeof(double) * S_NSLOTS, 0)) {
     c->err = "device allocation for the Newton workspace failed";
@@ -529,12 +751,19 @@ int read_scalars(gedmg_ctx* c, Work& w) {
 // Solve K x = b (CG with the Jacobi + coarse preconditioner; BiCGStab with
 // Jacobi on non-positive curvature).  K is the masked matrix and w.mask the
 // Dirichlet mask of this solve.  Returns iterations in *its.
-int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int* its) {
+// CG in three launches per iteration (the sparse product with partials of
+// p.q, the update, the p update), for systems large enough that the sparse
+// product, not launch latency, sets the pace; the host polls the residual
+// adaptively (each poll stalls the stream, so the next one is placed at 70 % of
+// the iterations that the observed decay rate still needs, 8 to 128 ahead).
+// Sets *curvature on non-positive curvature; w.hscal[3] receives b.b.
+int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int* its, bool* curvature) {
   const long n = w.ndof;
   const int gr = kRedBlocks;
   const int nd = c->dim + 1;
   int rc;
   *its = 0;
+  *curvature = false;
   GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
   GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
   GH(hipMemcpyAsync(w.r, w.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
@@ -547,20 +776,15 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
   GH(hipGetLastError());
   if ((rc = read_scalars(c, w))) return rc;
   const double bb = w.hscal[S_RR];
+  w.hscal[3] = bb;
   if (bb == 0.0) return GEDMG_OK;
   if (!std::isfinite(bb)) { c->err = "non-finite right-hand side"; return GEDMG_E_NONFINITE; }
   const double tol2 = rtol * rtol * bb;
   const int check = 8;
-  // CG polls the residual adaptively: each poll stalls the stream, so the next
-  // one is placed at 70 % of the iterations the observed decay rate still needs
-  // (between 8 and 128 iterations ahead)
   int next_poll = check, prev_it = 0;
   double prev_rr = bb;
-  bool use_bicg = false;
   for (int it = 1; it <= max_it; ++it) {
     const int ra = (it & 1) ? S_RZ : S_RZNEW, rb = (it & 1) ? S_RZNEW : S_RZ;
-    // three launches: q = K p with partials of p.q (kept apart from the
-    // update's partials), the update (alpha from those partials), the p update
     double* part_pap = w.part + 3 * kRedBlocks;
     if ((rc = spmv_part(c, w, K, w.p, w.q, w.p, part_pap))) return rc;
     hipLaunchKernelGGL(cg_update_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.x, w.r, w.p, w.q, w.dinv,
@@ -571,7 +795,8 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
     *its = it;
     if (it == next_poll || it == max_it) {
       if ((rc = read_scalars(c, w))) return rc;
-      if (w.hscal[S_FLAG] != 0.0) { use_bicg = true; break; }
+      w.hscal[3] = bb;
+      if (w.hscal[S_FLAG] != 0.0) { *curvature = true; return GEDMG_OK; }
       const double rr = w.hscal[S_RR];
       if (!std::isfinite(rr)) { c->err = "non-finite Krylov residual"; return GEDMG_E_NONFINITE; }
       if (rr <= tol2) return GEDMG_OK;
@@ -586,9 +811,65 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
       next_poll = it + ahead;
     }
   }
-  if (!use_bicg) { c->err = "CG reached the iteration limit"; return GEDMG_E_LINSOLVE; }
+  c->err = "CG reached the iteration limit";
+  return GEDMG_E_LINSOLVE;
+}
 
+int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int* its, int method = 0,
+           int* fallbacks = nullptr) {
+  const long n = w.ndof;
+  const int gr = kRedBlocks;
+  const int nd = c->dim + 1;
+  const int G = c->dim == 3 ? 32 : 16;
+  *its = 0;
+  if (method == 1) {  // BiCGStab requested (non-symmetric tangents)
+    hipLaunchKernelGGL(dot2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, w.b, w.b, nullptr, nullptr,
+                       n, w.part);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_BB, -1);
+    GH(hipGetLastError());
+    int rc0 = read_scalars(c, w);
+    if (rc0) return rc0;
+    w.hscal[3] = w.hscal[S_BB];
+    if (w.hscal[3] == 0.0) {
+      GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
+      return GEDMG_OK;
+    }
+    if (!std::isfinite(w.hscal[3])) { c->err = "non-finite right-hand side"; return GEDMG_E_NONFINITE; }
+  } else if (n >= kCoopMaxDofs) {
+    bool curvature = false;
+    const int rc1 = cg_multi(c, w, K, max_it, rtol, its, &curvature);
+    if (rc1 || !curvature) return rc1;
+    if (fallbacks) ++*fallbacks;
+  } else {
+  // CG with the Jacobi + coarse preconditioner in one cooperative launch
+  if (w.coop_blocks == 0) {
+    int occ = 0;
+    const void* fn = G == 32 ? (const void*)cg_coop_kernel<32> : (const void*)cg_coop_kernel<16>;
+    GH(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, 0));
+    // one block per compute unit (cheaper grid barriers)
+    const int per_cu = std::max(1, std::min(occ, 1));
+    const long need = std::max(1L, (n + 255) / 256);
+    w.coop_blocks = (int)std::min<long>({(long)c->num_cu * per_cu, need, (long)kCoopMaxBlocks});
+  }
+  CoopCgArgs ca{K, c->drowptr, c->dcol, w.b, w.dinv, w.mask, w.x, w.r, w.p, w.p1, w.q, w.cpart, w.cscal,
+                n, nd, max_it, rtol * rtol};
+  void* kargs[] = {&ca};
+  const void* fn = G == 32 ? (const void*)cg_coop_kernel<32> : (const void*)cg_coop_kernel<16>;
+  GH(hipLaunchCooperativeKernel(fn, dim3(w.coop_blocks), dim3(256), kargs, 0, c->stream));
+  GH(hipMemcpyAsync(w.hscal, w.cscal, sizeof(double) * 4, hipMemcpyDeviceToHost, c->stream));
+  GH(hipStreamSynchronize(c->stream));
+  *its = (int)w.hscal[0];
+  const int cg_status = (int)w.hscal[1];
+  if (cg_status == 0) return GEDMG_OK;
+  if (cg_status == 3) { c->err = "non-finite Krylov residual"; return GEDMG_E_NONFINITE; }
+  if (cg_status == 2) { c->err = "CG reached the iteration limit"; return GEDMG_E_LINSOLVE; }
+  // non-positive curvature (the tangent is not positive definite here)
+  if (fallbacks) ++*fallbacks;
+  }
   // BiCGStab from x = 0 with right Jacobi preconditioning.
+  int rc;
+  const int check = 8;
+  const double tol2 = rtol * rtol * w.hscal[3];  // w.hscal[3] = b.b
   const int cg_its = *its;
   GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
   GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
@@ -717,6 +998,10 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
     c->err = "solver limits must be positive";
     return GEDMG_E_ARG;
   }
+  if (o.krylov_method != 0 && o.krylov_method != 1) {
+    c->err = "unknown Krylov method";
+    return GEDMG_E_ARG;
+  }
   if (!(o.newton_rscale >= 0.0)) {
     c->err = "newton_rscale must be non-negative";
     return GEDMG_E_ARG;
@@ -792,8 +1077,10 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
   for (int it = 0; it <= max_it; ++it) {
     // residual (FP64) and tangent (FP64 or mixed)
     if (mixed) {
-      if ((rc = gedmg_assemble(c, u, phi, kappa, precision, w.Rmp, w.K, w.ktmp))) return rollback(rc);
-      if ((rc = gedmg_assemble(c, u, phi, kappa, GEDMG_FP64, w.R, nullptr, w.kt))) return rollback(rc);
+      // one pass: low-precision Hessian in the tangent, FP64 value and gradient
+      // for the residual and the history
+      const AssembleScratch sc{c->dx, c->djet, c->dphiq, c->dsens};
+      if ((rc = assemble_impl(c, u, phi, kappa, precision, w.R, w.K, w.kt, sc, false, true))) return rollback(rc);
     } else {
       if ((rc = gedmg_assemble(c, u, phi, kappa, GEDMG_FP64, w.R, w.K, w.kt))) return rollback(rc);
     }
@@ -801,8 +1088,21 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
     GH(hipGetLastError());
     const double res2 = sum_partials_host(c, w, &rc);
     if (rc) return rollback(rc);
-    if ((rc = gedmg_status(c))) return rollback(rc);
+    const int st = gedmg_status(c);
     const double res = std::sqrt(res2);
+    // A correction that inverts an element or makes the residual non-finite is
+    // halved (up to kMaxBacktracks times) before the step gives up: far from the
+    // solution the full Newton correction of a softening state can overshoot.
+    if ((st == GEDMG_E_JNONPOS || (st == GEDMG_OK && !std::isfinite(res))) && it > 0 &&
+        r.backtracks < kMaxBacktracks) {
+      hipLaunchKernelGGL(backtrack_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, u, phi, w.x, c->dim,
+                         c->n_nodes);
+      GH(hipGetLastError());
+      r.backtracks++;
+      --it;
+      continue;
+    }
+    if (st) return rollback(st);
     if (it < 32) r.res_norm[it] = res;
     r.newton_iters = it;
     if (!std::isfinite(res)) { c->err = "non-finite residual"; return rollback(GEDMG_E_NONFINITE); }
@@ -840,7 +1140,7 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
     double eta =
         o.krylov_forcing ? std::max(o.krylov_rtol, std::min(1e-3, res / std::max(res0, 1e-300))) : o.krylov_rtol;
     if (mixed) eta = std::max(eta, o.refine_rtol);
-    rc = krylov(c, w, w.K, o.max_krylov, eta, &its);
+    rc = krylov(c, w, w.K, o.max_krylov, eta, &its, o.krylov_method, &r.krylov_fallbacks);
     r.krylov_iters_total += its;
     if (rc) return rollback(rc);
     hipLaunchKernelGGL(update_fields_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, u, phi, w.x,

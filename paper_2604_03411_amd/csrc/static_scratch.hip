@@ -76,5 +76,5 @@ extern "C" int gedmg_assemble_static(gedmg_ctx* c, const double* u, const double
   }
   // sub-arrays at fixed offsets of the maximum size (all multiples of 256 bytes)
   const AssembleScratch sc{base, base + 3 * kStaticMaxQp, base + 13 * kStaticMaxQp, base + 14 * kStaticMaxQp};
-  return assemble_impl(c, u, phi, kappa_n, precision, R, K_vals, kappa_trial, sc, true);
+  return assemble_impl(c, u, phi, kappa_n, precision, R, K_vals, kappa_trial, sc, true, false);
 }

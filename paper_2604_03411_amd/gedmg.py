@@ -56,7 +56,9 @@ class SolverOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("max_krylov", C.c_int32), ("max_local", C.c_int32),
                 ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("krylov_rtol", C.c_double),
                 ("krylov_forcing", C.c_int32), ("refine_max", C.c_int32), ("refine_rtol", C.c_double),
-                ("scheme", C.c_int32), ("newton_rscale", C.c_double)]
+                ("scheme", C.c_int32), ("newton_rscale", C.c_double), ("krylov_method", C.c_int32)]
+
+KRYLOV = {"cg": 0, "bicgstab": 1}
 
 SCHEMES = {"monolithic": 0, "staggered": 1}
 
@@ -64,7 +66,7 @@ SCHEMES = {"monolithic": 0, "staggered": 1}
 # Defaults of gedmg_solver_opts (include/gedmg.h); the bindings pass every field.
 SOLVER_DEFAULTS = dict(max_newton=25, max_krylov=20000, max_local=100, newton_rtol=1e-10, newton_atol=0.0,
                        krylov_rtol=1e-12, krylov_forcing=True, refine_max=10, refine_rtol=1e-8,
-                       scheme="monolithic", newton_rscale=1.0)
+                       scheme="monolithic", newton_rscale=1.0, krylov_method="cg")
 
 
 def solver_opts(**kw):
@@ -77,15 +79,21 @@ def solver_opts(**kw):
         if sch not in SCHEMES:
             raise GedmgError(-1, f"unknown scheme {sch!r}")
         sch = SCHEMES[sch]
+    km = o["krylov_method"]
+    if isinstance(km, str):
+        if km not in KRYLOV:
+            raise GedmgError(-1, f"unknown Krylov method {km!r}")
+        km = KRYLOV[km]
     return SolverOpts(int(o["max_newton"]), int(o["max_krylov"]), int(o["max_local"]), float(o["newton_rtol"]),
                       float(o["newton_atol"]), float(o["krylov_rtol"]), 1 if o["krylov_forcing"] else 0,
-                      int(o["refine_max"]), float(o["refine_rtol"]), int(sch), float(o["newton_rscale"]))
+                      int(o["refine_max"]), float(o["refine_rtol"]), int(sch), float(o["newton_rscale"]), int(km))
 
 
 class NewtonReport(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("krylov_iters_total", C.c_int32),
                 ("n_yielded_qp", C.c_int32), ("status", C.c_int32),
-                ("res_norm", C.c_double * 32), ("reaction", C.c_double)]
+                ("res_norm", C.c_double * 32), ("reaction", C.c_double), ("backtracks", C.c_int32),
+                ("krylov_fallbacks", C.c_int32)]
 
 
 class AdjointReport(C.Structure):
@@ -353,7 +361,8 @@ class Context:
         rc = lib().gedmg_newton_step(self._h, C.byref(bc), C.byref(opts), prec, _dptr(pred), _dptr(u), _dptr(phi),
                                      _dptr(kappa), _dptr(rd), nr, C.byref(rep))
         out = dict(status=rc, newton_iters=rep.newton_iters, krylov_iters=rep.krylov_iters_total,
-                   n_yielded_qp=rep.n_yielded_qp, reaction=rep.reaction,
+                   n_yielded_qp=rep.n_yielded_qp, reaction=rep.reaction, backtracks=rep.backtracks,
+                   krylov_fallbacks=rep.krylov_fallbacks,
                    res_norm=list(rep.res_norm[: min(rep.newton_iters + 1, 32)]))
         if rc != 0 and raise_on_error:
             self._check(rc)

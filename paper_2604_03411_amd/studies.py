@@ -14,10 +14,15 @@ scalars (reaction, the largest history value) between increments.
   the gradient-enhanced model under the monolithic or the staggered scheme, on
   a coarse, a refined or a non-uniform mesh.  Stops when the largest damage
   reaches d_stop (the paper's 0.995) or the solver fails.
+* train_icnn: fitting both networks to a reaction-force curve of a cyclic
+  (load / unload / reload) homogeneous test through the load-path adjoint,
+  the use Sec. 4.2.1 describes for stress-stretch data (here synthetic: a
+  teacher network with perturbed parameters generates the targets).
 
 Usage:
     python -m paper_2604_03411_amd.studies single-element
     python -m paper_2604_03411_amd.studies plate [--steps 1000] [--total 80]
+    python -m paper_2604_03411_amd.studies train [--steps 40]
 (one JSON line per run on stdout).
 """
 from __future__ import annotations
@@ -102,14 +107,59 @@ def uniform_plate(mesh_kind="coarse", model="nonlocal", scheme="monolithic", n_s
                 steps=rows)
 
 
+def training_path(case, ctx, targets=None, checkpoint_every=6):
+    """The cyclic load path of a training case as a gedmg LoadPath.  Without
+    targets, they are computed by a forward run with the teacher's parameters."""
+    steps = case.n_steps
+    bcs = [W.cyclic_bc(case, n) for n in range(1, steps + 1)]
+    du = np.stack([W.cyclic_increment(case, n) for n in range(1, steps + 1)])
+    rd = W.reaction_dofs(case)
+    if targets is None:
+        ctx.set_params(case.extra["theta_e_star"], case.extra["theta_y_star"])
+        u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+        targets = [ctx.newton_step(u, phi, kap, *bcs[n - 1], reaction_dofs=rd, predictor_du=du[n - 1])["reaction"]
+                   for n in range(1, steps + 1)]
+        ctx.set_params(case.theta_e, case.theta_y)
+    return G.LoadPath(case.u, case.phi, case.kappa, bcs, rd, targets, predictor_du=du), checkpoint_every
+
+
+def train_icnn(case=None, iters=40, lr=2e-2, log=None):
+    """Fit the raw parameters of both networks to the teacher's reaction
+    curve of the cyclic path with Adam, the gradient of the load-path loss
+    coming from the library's adjoint (torch.autograd.Function LoadPathLoss).
+    Returns the loss history."""
+    case = case or W.training_case()
+    ctx = G.Context.from_case(case)
+    path, ce = training_path(case, ctx)
+    te = torch.tensor(case.theta_e, dtype=torch.float64, requires_grad=True)
+    ty = torch.tensor(case.theta_y, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([te, ty], lr=lr)
+    hist = []
+    for it in range(iters):
+        opt.zero_grad()
+        loss = G.load_path_loss(ctx, te, ty, path, ce)
+        loss.backward()
+        hist.append(float(loss))
+        if log:
+            log(f"iteration {it}: loss {hist[-1]:.4e}")
+        opt.step()
+    ctx.close()
+    return dict(study="training", case=case.name, iters=iters, lr=lr, loss=hist,
+                targets=[float(t) for t in path.targets])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("study", choices=["single-element", "plate"])
+    ap.add_argument("study", choices=["single-element", "plate", "train"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--total", type=float, default=None)
     ap.add_argument("--every", type=int, default=1, help="keep every k-th step in the output")
     args = ap.parse_args()
     torch.cuda.set_device(0)
+    if args.study == "train":
+        r = train_icnn(iters=args.steps or 40, log=lambda m: print(f"[train] {m}", file=sys.stderr, flush=True))
+        print(json.dumps(r), flush=True)
+        return
     if args.study == "single-element":
         for eta, kd in ((1.0, 1.0), (10.0, 1.0), (100.0, 1.0), (10.0, 0.0), (10.0, 2.0)):
             r = single_element(eta, kd, args.steps or 50, args.total or 0.5)

@@ -38,6 +38,13 @@ def test_fp64_assembly_matches_oracle(G, cfg):
     eR, eK, ek = rel_err(R.cpu().numpy(), R0), rel_err(Kg.data, K0.data), rel_err(kt.cpu().numpy(), k0)
     print(f"  rel err R {eR:.2e} K {eK:.2e} kappa {ek:.2e}; yielded {(k0 > kap).mean():.2f}", flush=True)
     assert eR <= TOL and eK <= TOL and ek <= TOL
+    # residual only: the network gradient then comes from the reverse-mode jet
+    R1, K1, k1 = ctx.assemble(*ctx.fields(u, phi, kap), "fp64", tangent=False)
+    sync()
+    assert K1 is None and ctx.status() == 0
+    eR1, ek1 = rel_err(R1.cpu().numpy(), R0), rel_err(k1.cpu().numpy(), k0)
+    print(f"  residual only: rel err R {eR1:.2e} kappa {ek1:.2e}", flush=True)
+    assert eR1 <= TOL and ek1 <= TOL
     ctx.close()
 
 

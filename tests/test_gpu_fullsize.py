@@ -108,8 +108,11 @@ def test_full_size_box_newton_path_matches_closed_form():
     for n in range(1, case.n_steps + 1):
         u.copy_(torch.as_tensor(W.affine_stretch_guess(case, n), device=ctx.dev))
         bd, bv = W.affine_stretch_bc(case, n)
+        # the uniform damage mode is the softest (stiffness ~ beta_d (1 - kappa_phi), about
+        # 1e-6 of beta_d): a residual of 1e-11 over the 9801 damage dofs can leave phi 2e-6
+        # off the closed form, so the box is solved one order further
         rep = ctx.newton_step(u, phi, kap, bd, bv, "fp64", reaction_dofs=W.reaction_dofs(case),
-                              newton_rtol=0.0, newton_atol=1e-11, krylov_rtol=1e-13)
+                              newton_rtol=0.0, newton_atol=1e-12, krylov_rtol=1e-13)
         sync()
         print(f"  step {n}: iters {rep['newton_iters']} krylov {rep['krylov_iters']} "
               f"res {rep['res_norm'][-1]:.2e}", flush=True)

@@ -98,3 +98,46 @@ def test_inexact_and_exact_linear_solves_reach_the_same_states():
         assert rel_err(u1, u0) < 1e-8 and rel_err(p1, p0) < 1e-6 and rel_err(k1, k0) < 1e-6
         assert abs(r1["reaction"] - r0["reaction"]) <= 1e-8 * abs(r0["reaction"])
     assert sum(r["krylov_iters"] for *_, r in inexact) < sum(r["krylov_iters"] for *_, r in exact)
+
+
+def test_bicgstab_with_non_symmetric_tangent_matches_oracle():
+    """gamma_d = 0.5 makes the history term of the tangent non-symmetric above
+    kappa_d (the symmetric form needs gamma_d = 1): the load steps solved with
+    BiCGStab (krylov_method) match the oracle's Newton with a direct sparse
+    solve, which does not depend on symmetry."""
+    from paper_2604_03411_amd import gedmg as G
+    case = W.make_case(3, n=16)
+    case.n_steps = 8
+    case.material = dict(case.material, gamma_d=0.5)
+    print("[newton] notched plate q4 16x16, gamma_d = 0.5, BiCGStab", flush=True)
+    gpu = run_gpu_path(G, case, 3, W.uniaxial_bc, predictor_du=W.uniaxial_increment(case),
+                       krylov_method="bicgstab")
+    recs = solve.load_path(case, fem.Model(case), steps=3, rtol=0.0, atol=ATOL)
+    for (ug, pg, kg, rep), r in zip(gpu, recs):
+        uo, po = fem.split_dofs(r["d"], 2)
+        assert abs(rep["reaction"] - r["reaction"]) <= 1e-8 * abs(r["reaction"])
+        assert rel_err(ug, uo) < 1e-8 and rel_err(pg, po) < 1e-6 and rel_err(kg, r["kappa"]) < 1e-6
+
+
+def test_cg_falls_back_to_bicgstab_on_non_positive_curvature():
+    """The local monolithic single-element step into softening has an
+    indefinite tangent f_d (psi_FF - eta_d psi_F (x) psi_F): CG meets
+    non-positive curvature and BiCGStab takes over (reported per step)."""
+    from paper_2604_03411_amd import gedmg as G
+    case = W.single_element_case(eta_d=10.0, kappa_d=1.0, n_steps=12)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    du = W.uniaxial_increment(case)
+    fallbacks = 0
+    for n in range(1, 7):
+        bd, bv = W.symmetric_tension_bc(case, n)
+        rep = ctx.newton_step(u, phi, kap, bd, bv, predictor_du=du, raise_on_error=False, max_newton=8,
+                              newton_rtol=1e-12, newton_atol=0.0, newton_rscale=0.0)
+        sync()
+        fallbacks += rep["krylov_fallbacks"]
+        print(f"  step {n}: status {rep['status']} iters {rep['newton_iters']} "
+              f"fallbacks {rep['krylov_fallbacks']}", flush=True)
+        if rep["status"] != 0:
+            break
+    assert fallbacks >= 1
+    ctx.close()
