@@ -436,3 +436,73 @@ def symmetric_tension_bc(case: Case, step: int):
         dofs.append(_dof(allnodes, m.dim, m.dim))
         vals.append(np.zeros(m.n_nodes))
     return np.concatenate(dofs).astype(np.int32), np.concatenate(vals)
+
+
+def training_case(n: int = 4, seed: int = 5, teacher_std: float = 0.02, beta_d: float = 10.0) -> Case:
+    """Synthetic stress-stretch data for fitting the two networks through the
+    load-path adjoint: an n x n Q4 bar (unit square) pulled uniaxially along a
+    cyclic path with unloading and reloading (loading to 5 %, back to 2 %, to
+    9 %, back to 4 %, to 12 %), the networks of the 128 x 128 adjoint workload
+    (3-32-32-1 energy, 1-32-32-1 yield) as the starting point and a teacher
+    with the raw parameters perturbed by N(0, teacher_std^2) (seed 77) whose
+    reactions are the targets.  The homogeneous states have phi = kappa, so
+    the response does not depend on beta_d; beta_d = 10 (instead of 1000)
+    keeps the uniform-damage mode of the tangent, and with it the gradient,
+    well conditioned."""
+    base = make_case(5, n=n)
+    base.material = dict(base.material, beta_d=beta_d)
+    levels = np.concatenate([np.linspace(0.01, 0.05, 5), [0.035, 0.02], np.linspace(0.034, 0.09, 5),
+                             [0.065, 0.04], np.linspace(0.06, 0.12, 4)])
+    trng = np.random.default_rng(77)
+    te_star = base.theta_e + trng.normal(0.0, teacher_std, size=base.theta_e.shape)
+    ty_star = base.theta_y + trng.normal(0.0, teacher_std, size=base.theta_y.shape)
+    return Case(f"q4_{n}x{n}_cyclic_training", base.mesh, base.material, base.energy, base.yield_,
+                base.theta_e, base.theta_y, base.u, base.phi, base.kappa, len(levels),
+                dict(levels=levels, theta_e_star=te_star, theta_y_star=ty_star, seed=seed, total_disp=1.0))
+
+
+def cyclic_bc(case: Case, step: int):
+    """uniaxial_bc with the right-edge displacement of the cyclic path."""
+    dofs, vals = uniaxial_bc(case, step)
+    lvl = case.extra["levels"][step - 1]
+    return dofs, np.where(vals != 0.0, lvl, vals)
+
+
+def cyclic_increment(case: Case, step: int) -> np.ndarray:
+    """Predictor increment of step `step` of the cyclic path (the change of the
+    boundary displacement spread linearly in x)."""
+    lv = case.extra["levels"]
+    prev = lv[step - 2] if step > 1 else 0.0
+    return uniaxial_increment(case) * case.n_steps * (lv[step - 1] - prev)
+
+
+def strip_case(nx: int = 20, eta_d: float = 0.05, kappa_d: float = 0.1, c_d: float = 1.0,
+               beta_d: float = 1000.0, weak: float = 0.5, E: float = 210.0, nu: float = 0.3) -> Case:
+    """A Q4 strip of nx unit elements (length nx, height 1) of the closed-form
+    model, with the middle element weakened by an initial history weak > kappa_d
+    (f_d < 1 there): under tension the damage localises in it while the rest of
+    the strip unloads, so that on a long strip the force-displacement path
+    turns back (snap-back) and only arc-length continuation can follow it.
+    Loading: u_x = 0 on the left edge, u_y = 0 at the origin, u_x = lambda on
+    the right edge (unit pattern, see arclength_pattern)."""
+    mesh = q4_grid(nx, 1, float(nx), 1.0)
+    mat = _closed_material(E, nu, eta_d, kappa_d, c_d, beta_d)
+    u, phi, kap = _uniaxial_fields(mesh)
+    mid = nx // 2
+    kap[mid, :] = weak
+    phi[:] = 0.0
+    return Case(f"q4_strip_{nx}x1", mesh, mat, CLOSED_FORM, IDENTITY_YIELD, np.zeros(0), np.zeros(0), u, phi, kap,
+                0, dict(total_disp=1.0))
+
+
+def arclength_pattern(case: Case):
+    """Prescribed dofs of the uniaxial loading with their values per unit load
+    factor: 0 on the left edge and at the origin, 1 on the right edge."""
+    dofs, vals = uniaxial_bc(dataclass_replace_steps(case), 1)
+    return dofs, np.where(vals != 0.0, 1.0, 0.0)
+
+
+def dataclass_replace_steps(case: Case) -> Case:
+    """A shallow copy of case with one load step of unit total displacement."""
+    import dataclasses
+    return dataclasses.replace(case, n_steps=1, extra=dict(case.extra, total_disp=1.0))
