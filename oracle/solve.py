@@ -147,3 +147,72 @@ def loss_and_gradient(case, records, targets, theta_e=None, theta_y=None, react_
         g_y += gy
         abar = gk.detach()
     return loss, g_e.numpy(), g_y.numpy()
+
+
+def arclength_step(model, mesh, d, lam, kappa_n, bc_dofs, bc_unit, ds, psi=1.0, prev=None, rtol=1e-10,
+                   atol=None, max_iter=25, rscale=1.0):
+    """One increment of arc-length continuation for displacement-controlled
+    loading (the paper's arc-length remark in Sec. 3.2 and its use in Sec. 5.1):
+    the prescribed dofs carry lam * bc_unit, and the load factor lam is an
+    unknown next to the free dofs, tied by the constraint
+    ||Delta d_f||^2 + psi^2 Delta lam^2 = ds^2 (Riks: the corrector iterates in
+    the plane normal to the predictor).
+
+    Predictor: the previous increment `prev` = (Delta d_f, Delta lam) scaled to
+    length ds (secant); for the first increment (prev None) the tangent
+    t = -K_ff^-1 K_fp bc_unit of the equilibrium path with the history held at
+    kappa_n, scaled to ds, forward.  (At a converged state the yielded points sit
+    on the yield surface to rounding, so whether a loading or an elastic
+    tangent is taken there would be decided by rounding; the secant and the
+    held-history tangent are defined without that decision.)  Corrector:
+    a = -K_ff^-1 R_f, b = -K_ff^-1 K_fp bc_unit,
+    dlam = -(Dd . a) / (Dd . b + psi^2 Dlam), dd = a + dlam b, with (Dd, Dlam)
+    the predictor.  The history is updated inside every iteration (monolithic).
+    Converged when ||R_f|| <= max(rtol * max(rscale, ||R_f^0||), atol), R_f^0
+    the residual at the predictor.
+
+    Returns (d, lam, kappa_{n+1}, (Delta d_f, Delta lam), residual history,
+    converged)."""
+    atol = default_atol(mesh) if atol is None else atol
+    free = np.ones(mesh.ndof, bool)
+    free[bc_dofs] = False
+    uhat = np.zeros(mesh.ndof)
+    uhat[bc_dofs] = bc_unit
+    d = np.array(d, dtype=np.float64, copy=True)
+    d[bc_dofs] = lam * np.asarray(bc_unit)
+    d0f = d[free].copy()
+    lam0 = lam
+    if prev is not None:
+        scale = ds / np.sqrt(float(prev[0] @ prev[0]) + psi * psi * prev[1] ** 2)
+        dd_p = scale * np.asarray(prev[0])
+        dlam_p = scale * prev[1]
+    else:
+        R, K, _ = fem.assemble(model, mesh, d, kappa_n, update_history=False)
+        Kff = K[free][:, free].tocsc()
+        t = spla.spsolve(Kff, -(K @ uhat)[free])
+        dlam_p = ds / np.sqrt(t @ t + psi * psi)
+        dd_p = dlam_p * t
+    lam = lam0 + dlam_p
+    d[free] = d0f + dd_p
+    d[bc_dofs] = lam * np.asarray(bc_unit)
+    hist = []
+    res0 = None
+    for it in range(max_iter + 1):
+        R, K, kt = fem.assemble(model, mesh, d, kappa_n)
+        Rf = R[free]
+        res = float(np.linalg.norm(Rf))
+        res0 = res if res0 is None else res0
+        hist.append(res)
+        if res <= max(rtol * max(rscale, res0), atol):
+            return d, lam, kt, (d[free] - d0f, lam - lam0), hist, True
+        if it == max_iter or not np.isfinite(res):
+            break
+        Kff = K[free][:, free].tocsc()
+        lu = spla.splu(Kff)
+        a = lu.solve(-Rf)
+        b = lu.solve(-(K @ uhat)[free])
+        dl = -float(dd_p @ a) / float(dd_p @ b + psi * psi * dlam_p)
+        d[free] += a + dl * b
+        lam += dl
+        d[bc_dofs] = lam * np.asarray(bc_unit)
+    return d, lam, kt, (d[free] - d0f, lam - lam0), hist, False

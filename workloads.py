@@ -476,29 +476,32 @@ def cyclic_increment(case: Case, step: int) -> np.ndarray:
     return uniaxial_increment(case) * case.n_steps * (lv[step - 1] - prev)
 
 
-def strip_case(nx: int = 20, eta_d: float = 0.05, kappa_d: float = 0.1, c_d: float = 1.0,
-               beta_d: float = 1000.0, weak: float = 0.5, E: float = 210.0, nu: float = 0.3) -> Case:
+def strip_case(nx: int = 20, eta_d: float = 2.0, kappa_d: float = 0.1, c_d: float = 1.0,
+               beta_d: float = 1000.0, neck: float = 0.1, E: float = 210.0, nu: float = 0.3) -> Case:
     """A Q4 strip of nx unit elements (length nx, height 1) of the closed-form
-    model, with the middle element weakened by an initial history weak > kappa_d
-    (f_d < 1 there): under tension the damage localises in it while the rest of
-    the strip unloads, so that on a long strip the force-displacement path
-    turns back (snap-back) and only arc-length continuation can follow it.
+    model, necked at mid-length (the two top nodes there lowered by `neck`):
+    under tension the damage starts and localises in the neck while the rest
+    of the strip unloads; with nx = 20 and eta_d = 2 the end displacement falls
+    with the force past the force maximum (snap-back), which only arc-length
+    continuation follows.
     Loading: u_x = 0 on the left edge, u_y = 0 at the origin, u_x = lambda on
     the right edge (unit pattern, see arclength_pattern)."""
     mesh = q4_grid(nx, 1, float(nx), 1.0)
+    mid = nx // 2
+    top = np.nonzero((np.abs(mesh.X[1] - 1.0) < 1e-12) & ((np.abs(mesh.X[0] - mid) < 1e-12)
+                                                          | (np.abs(mesh.X[0] - mid - 1) < 1e-12)))[0]
+    mesh.X[1, top] -= neck
     mat = _closed_material(E, nu, eta_d, kappa_d, c_d, beta_d)
     u, phi, kap = _uniaxial_fields(mesh)
-    mid = nx // 2
-    kap[mid, :] = weak
-    phi[:] = 0.0
     return Case(f"q4_strip_{nx}x1", mesh, mat, CLOSED_FORM, IDENTITY_YIELD, np.zeros(0), np.zeros(0), u, phi, kap,
                 0, dict(total_disp=1.0))
 
 
-def arclength_pattern(case: Case):
-    """Prescribed dofs of the uniaxial loading with their values per unit load
-    factor: 0 on the left edge and at the origin, 1 on the right edge."""
-    dofs, vals = uniaxial_bc(dataclass_replace_steps(case), 1)
+def arclength_pattern(case: Case, bc_fn=None):
+    """Prescribed dofs of a displacement-controlled loading with their values
+    per unit load factor: 1 where bc_fn (default uniaxial_bc) moves a dof, 0
+    where it holds one."""
+    dofs, vals = (bc_fn or uniaxial_bc)(dataclass_replace_steps(case), 1)
     return dofs, np.where(vals != 0.0, 1.0, 0.0)
 
 
