@@ -137,9 +137,12 @@ typedef struct {
    * states whose whole residual is scaled by a tiny degradation f_d. */
   double newton_rscale;
   /* Krylov method of the Newton solves: 0 (default) CG with the Jacobi + coarse
-   * preconditioner, switching to BiCGStab when it meets non-positive curvature;
-   * 1 BiCGStab with Jacobi from the start, for tangents that are not symmetric
-   * (gamma_d != 1, or history in the window kappa_n < kappa <= kappa_d). */
+   * preconditioner, switching to BiCGStab when it meets non-positive curvature
+   * or reaches max_krylov without converging (each switch counts in
+   * krylov_fallbacks); 1 BiCGStab with Jacobi from the start, for tangents that
+   * are not symmetric (gamma_d != 1, or points yielding with kappa below
+   * kappa_d, where the history enters the damage rows but not the displacement
+   * rows). */
   int32_t krylov_method;
 } gedmg_solver_opts;
 
@@ -291,6 +294,40 @@ int gedmg_newton_step(gedmg_ctx* ctx, const gedmg_dirichlet* bc, const gedmg_sol
                       int precision, const double* predictor_du, double* u, double* phi, double* kappa,
                       const int32_t* reaction_dofs, int32_t n_reaction,
                       gedmg_newton_report* report);
+
+/* One increment of arc-length continuation for displacement-controlled loading
+ * (the paper solves its strongly softening single-element study with an
+ * arc-length continuation, Sec. 5.1; Sec. 3.2 names the approach): the
+ * prescribed dofs carry lambda times their unit values pattern->value, and the
+ * load factor lambda is solved for together with the free dofs under
+ * ||Delta d_f||^2 + psi^2 Delta lambda^2 = ds^2, so the path is followed
+ * through limit points of the load factor (snap-back), where displacement
+ * control has no solution nearby.  Riks' scheme: the predictor is the previous
+ * increment scaled to length ds (secant); for a first increment (increment all
+ * zero) it is the path tangent t = -K_ff^-1 K_fp uhat with the history held at
+ * kappa, scaled to ds, with Delta lambda > 0.  (The yielded points of a
+ * converged state sit on the yield surface to rounding; neither predictor asks
+ * whether they load.)  The corrector iterates in the plane normal to the predictor with
+ * two Krylov solves per iteration, a = -K_ff^-1 R_f and b = -K_ff^-1 K_fp uhat,
+ * dlambda = -(Dd . a) / (Dd . b + psi^2 Dlambda), dd = a + dlambda b, until the
+ * Newton test of gedmg_newton_step holds.  FP64, monolithic history (opts->
+ * scheme and refine_* are ignored).
+ *   pattern     Dirichlet set: device dof indices and their unit values uhat
+ *   ds, psi     arc length (> 0) and load-factor scale (>= 0; 0: cylindrical)
+ *   lambda      host, in: the load factor of the state passed in; out: the
+ *               converged one
+ *   increment   device [ndof + 1], in: the previous increment (free dofs in the
+ *               node-major dof layout, zero on Dirichlet rows, Delta lambda
+ *               last; all zeros for a first increment); out: this increment
+ *   u, phi, kappa, reaction_dofs, n_reaction, report: as for gedmg_newton_step
+ *               (u, phi, kappa and lambda restored on failure)
+ * Synchronises the stream; allocates four vectors of workspace on its first
+ * call for a context.  Errors: those of gedmg_newton_step, GEDMG_E_LINSOLVE
+ * when the constraint cannot be solved (Dd . b + psi^2 Dlambda = 0). */
+int gedmg_arclength_step(gedmg_ctx* ctx, const gedmg_dirichlet* pattern, const gedmg_solver_opts* opts,
+                         double ds, double psi, double* lambda, double* increment, double* u, double* phi,
+                         double* kappa, const int32_t* reaction_dofs, int32_t n_reaction,
+                         gedmg_newton_report* report);
 
 /* Gradient of the load-path loss L = sum_n (r_n - t_n)^2, r_n the reaction of
  * step n, with respect to the raw parameters of both networks (the paper

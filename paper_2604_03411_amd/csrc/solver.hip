@@ -11,8 +11,6 @@
 // Sparse kernels are deterministic: fixed grids, per-block partial sums in a
 // fixed order, one-block final reductions; Krylov scalars stay on the device
 // and the host polls the residual norm only every few iterations.
-#include <hip/hip_cooperative_groups.h>
-
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -81,6 +79,50 @@ __global__ void set_dirichlet_kernel(double* u, double* phi, const int32_t* dof,
   else
     phi[node] = val[i];
   mask[d] = 1;
+}
+
+// Prescribed dofs at lambda times their unit values (arc-length continuation).
+__global__ void set_dirichlet_scaled_kernel(double* u, double* phi, const int32_t* dof, const double* val,
+                                            double lambda, int n, int dim, int n_nodes) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int d = dof[i];  // range checked by set_mask_kernel before the first use
+  const int node = d / (dim + 1), c = d % (dim + 1);
+  if (c < dim)
+    u[(long)c * n_nodes + node] = lambda * val[i];
+  else
+    phi[node] = lambda * val[i];
+}
+
+__global__ void scatter_kernel(double* y, const int32_t* idx, const double* val, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[idx[i]] = val[i];
+}
+
+// b = -y with Dirichlet rows zeroed.
+__global__ void masked_neg_kernel(const double* y, const uint8_t* mask, double* b, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = mask[i] ? 0.0 : -y[i];
+}
+
+__global__ void axpy_scalar_kernel(double* y, double alpha, const double* x, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = fma(alpha, x[i], y[i]);
+}
+
+__global__ void scale_copy_kernel(double* y, double alpha, const double* x, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = alpha * x[i];
+}
+
+// inc = (u, phi) - (ub, phib) in the node-major dof layout, zero on Dirichlet rows.
+__global__ void field_increment_kernel(const double* u, const double* phi, const double* ub, const double* phib,
+                                       const uint8_t* mask, double* inc, int dim, int n_nodes) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_nodes * (dim + 1)) return;
+  const int node = (int)(i / (dim + 1)), c = (int)(i % (dim + 1));
+  const double v = (c < dim) ? u[(long)c * n_nodes + node] - ub[(long)c * n_nodes + node] : phi[node] - phib[node];
+  inc[i] = mask[i] ? 0.0 : v;
 }
 
 __global__ void update_fields_kernel(double* u, double* phi, const double* delta, int dim, int n_nodes) {
@@ -335,199 +377,6 @@ __global__ void cg_p_kernel(double* p, const double* r, const double* dinv, cons
   }
 }
 
-// ---- CG in one cooperative launch.  The whole preconditioned CG runs in one
-// kernel whose blocks are all resident (cooperative launch) and meet at grid
-// barriers, two per iteration, instead of three dependent launches per
-// iteration: on systems of tens of thousands of dofs the iteration is bound
-// by launch latency, not by the sparse product.
-//   phase A: from the partial sums of the last update, every block forms
-//            cc = (chi.r)/E, (r.z) = r.D^-1.r + cc (chi.r), beta and the
-//            convergence test; the search direction p_new = z + beta p_old,
-//            z = D^-1 r + cc chi, is formed on the fly for every column the
-//            product reads (rows write their own entry into the other p
-//            buffer), q = K p_new and partial sums of p_new.q;
-//   phase B: alpha = (r.z)/(p.q) from those partials; x += alpha p_new,
-//            r -= alpha q, partial sums of r.D^-1.r, r.r and chi.r.
-// Every block sums the partials in the same order, so the scalars and the
-// exit decisions (converged, non-positive curvature, non-finite, iteration
-// limit) are identical in every block and all blocks leave the loop together.
-namespace cgk = cooperative_groups;
-
-struct CoopCgArgs {
-  const double* K;
-  const int32_t* rowptr;
-  const int32_t* col;
-  const double* b;       // right-hand side (prescribed rows zero)
-  const double* dinv;
-  const uint8_t* mask;
-  double* x;
-  double* r;
-  double* p0;
-  double* p1;
-  double* q;
-  double* part;          // [5][gridDim.x] partial sums
-  double* scal;          // out: iterations, status (0 converged, 1 curvature, 2 limit, 3 non-finite), r.r
-  long n;
-  int nd;
-  int max_it;
-  double tol2_rel;       // converged when r.r <= tol2_rel * b.b
-};
-
-__device__ __forceinline__ void block_sums3(const double* part, int nb, double* sh, double* bc, double& t1,
-                                            double& t2, double& t3) {
-  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    s1 += part[i];
-    s2 += part[nb + i];
-    s3 += part[2 * nb + i];
-  }
-  const double a1 = block_sum(s1, sh);
-  const double a2 = block_sum(s2, sh);
-  const double a3 = block_sum(s3, sh);
-  if (threadIdx.x == 0) {
-    bc[0] = a1;
-    bc[1] = a2;
-    bc[2] = a3;
-  }
-  __syncthreads();
-  t1 = bc[0];
-  t2 = bc[1];
-  t3 = bc[2];
-  __syncthreads();
-}
-
-template <int G>
-__global__ __launch_bounds__(256) void cg_coop_kernel(CoopCgArgs a) {
-  __shared__ double sh[8];
-  __shared__ double bc[3];
-  cgk::grid_group grid = cgk::this_grid();
-  const int nb = gridDim.x;
-  const long n = a.n;
-  const int nd = a.nd;
-  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x, nthr = (long)nb * blockDim.x;
-  double* ps = a.part;            // [3][nb]: r.D^-1.r, r.r, chi.r
-  double* pq_part = a.part + 3 * (long)nb;
-  double* pe_part = a.part + 4 * (long)nb;
-  // ---- x = 0, r = b; partials of chi.K.chi and of the three sums of r
-  {
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0, e = 0.0;
-    for (long i = tid; i < n; i += nthr) {
-      const double ri = a.b[i];
-      a.x[i] = 0.0;
-      a.r[i] = ri;
-      s1 += ri * a.dinv[i] * ri;
-      s2 += ri * ri;
-      if (chi(i, nd, a.mask)) {
-        s3 += ri;
-        for (int j = a.rowptr[i]; j < a.rowptr[i + 1]; ++j)
-          if (chi(a.col[j], nd, a.mask)) e += a.K[j];
-      }
-    }
-    double t = block_sum(s1, sh);
-    if (threadIdx.x == 0) ps[blockIdx.x] = t;
-    t = block_sum(s2, sh);
-    if (threadIdx.x == 0) ps[nb + blockIdx.x] = t;
-    t = block_sum(s3, sh);
-    if (threadIdx.x == 0) ps[2 * nb + blockIdx.x] = t;
-    t = block_sum(e, sh);
-    if (threadIdx.x == 0) pe_part[blockIdx.x] = t;
-  }
-  __threadfence();
-  grid.sync();
-  double E, bb;
-  {
-    double t1, t2, t3;
-    block_sums3(ps, nb, sh, bc, t1, bb, t3);
-    double se = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) se += pe_part[i];
-    const double te = block_sum(se, sh);
-    if (threadIdx.x == 0) bc[0] = te;
-    __syncthreads();
-    E = bc[0];
-    __syncthreads();
-  }
-  const double tol2 = a.tol2_rel * bb;
-  double rz_old = 0.0;
-  int status = 2, it = 0;
-  double rr = bb;
-  const int lane = threadIdx.x % G;
-  const long groups = (long)nb * (blockDim.x / G);
-  for (;; ++it) {
-    // ---- phase A
-    double S1, S2, S3;
-    block_sums3(ps, nb, sh, bc, S1, S2, S3);
-    rr = S2;
-    if (!(S2 == S2) || S2 > 1e300) { status = 3; break; }
-    if (S2 <= tol2) { status = 0; break; }
-    if (it >= a.max_it) { status = 2; break; }
-    const double cc = (E > 0.0) ? S3 / E : 0.0;
-    const double rz_new = S1 + cc * S3;
-    const bool first = it == 0;
-    const double beta = (!first && rz_old != 0.0) ? rz_new / rz_old : 0.0;
-    const double* pold = (it & 1) ? a.p1 : a.p0;
-    double* pnew = (it & 1) ? a.p0 : a.p1;
-    double acc = 0.0;
-    for (long row = (long)blockIdx.x * (blockDim.x / G) + threadIdx.x / G; row < n; row += groups) {
-      double sacc = 0.0;
-      for (int j = a.rowptr[row] + lane; j < a.rowptr[row + 1]; j += G) {
-        const int c = a.col[j];
-        const double z = a.dinv[c] * a.r[c] + (chi(c, nd, a.mask) ? cc : 0.0);
-        const double pc = first ? z : fma(beta, pold[c], z);
-        sacc = fma(a.K[j], pc, sacc);
-      }
-#pragma unroll
-      for (int o = G / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, G);
-      if (lane == 0) {
-        const double z = a.dinv[row] * a.r[row] + (chi(row, nd, a.mask) ? cc : 0.0);
-        const double pr = first ? z : fma(beta, pold[row], z);
-        pnew[row] = pr;
-        a.q[row] = sacc;
-        acc = fma(pr, sacc, acc);
-      }
-    }
-    {
-      const double t = block_sum(acc, sh);
-      if (threadIdx.x == 0) pq_part[blockIdx.x] = t;
-    }
-    rz_old = rz_new;
-    __threadfence();
-    grid.sync();
-    // ---- phase B
-    double spq = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) spq += pq_part[i];
-    const double tpq = block_sum(spq, sh);
-    if (threadIdx.x == 0) bc[0] = tpq;
-    __syncthreads();
-    const double pq = bc[0];
-    __syncthreads();
-    if (!(pq > 0.0)) { status = 1; break; }
-    const double alpha = rz_new / pq;
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (long i = tid; i < n; i += nthr) {
-      a.x[i] = fma(alpha, pnew[i], a.x[i]);
-      const double ri = fma(-alpha, a.q[i], a.r[i]);
-      a.r[i] = ri;
-      s1 += ri * a.dinv[i] * ri;
-      s2 += ri * ri;
-      if (chi(i, nd, a.mask)) s3 += ri;
-    }
-    double t = block_sum(s1, sh);
-    if (threadIdx.x == 0) ps[blockIdx.x] = t;
-    t = block_sum(s2, sh);
-    if (threadIdx.x == 0) ps[nb + blockIdx.x] = t;
-    t = block_sum(s3, sh);
-    if (threadIdx.x == 0) ps[2 * nb + blockIdx.x] = t;
-    __threadfence();
-    grid.sync();
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.scal[0] = (double)it;
-    a.scal[1] = (double)status;
-    a.scal[2] = rr;
-    a.scal[3] = bb;
-  }
-}
-
 __global__ void precond_kernel(double* z, const double* r, const double* dinv, long n) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     z[i] = dinv[i] * r[i];
@@ -624,17 +473,12 @@ struct Work {
   double *v = nullptr, *t = nullptr, *r0 = nullptr, *dinv = nullptr;
   double *ub = nullptr, *phib = nullptr;
   double *part = nullptr, *scal = nullptr, *hscal = nullptr;
-  double *cpart = nullptr, *cscal = nullptr;  // cooperative CG: partial sums, results
-  double* p1 = nullptr;                       // second search-direction buffer (cooperative CG)
   uint8_t* mask = nullptr;
-  int coop_blocks = 0;                        // grid of the cooperative CG (0: not sized yet)
+  // arc-length continuation (allocated on its first use): the unit loading
+  // pattern, the predictor, the two corrector solutions and K times the pattern
+  double *al_uh = nullptr, *al_dp = nullptr, *al_a = nullptr, *al_y = nullptr;
 };
 
-constexpr int kCoopMaxBlocks = 4096;
-// Systems from this many dofs on are solved with the three-launch CG: there the
-// sparse product sets the pace and the cooperative grid (one to four blocks per
-// compute unit) has too few loads in flight for it.
-constexpr long kCoopMaxDofs = 1L << 18;
 
 }  // namespace
 
@@ -658,7 +502,7 @@ void release_newton_work(gedmg_ctx* c) {
       Work& w = h[i]->w;
       void* ptrs[] = {w.K, w.Kmp, w.R, w.Rmp, w.kt, w.ktmp, w.b, w.x, w.r, w.z, w.p, w.q,
                       w.v, w.t, w.r0, w.dinv, w.ub, w.phib, w.part, w.scal, w.mask,
-                      w.cpart, w.cscal, w.p1};
+                      w.al_uh, w.al_dp, w.al_a, w.al_y};
       for (void* p : ptrs)
         if (p) (void)hipFree(p);
       if (w.hscal) (void)hipHostFree(w.hscal);
@@ -689,8 +533,7 @@ int ensure_work(gedmg_ctx* c, Work** out) {
       al(&w.z, w.ndof) || al(&w.p, w.ndof) || al(&w.q, w.ndof) || al(&w.v, w.ndof) ||
       al(&w.t, w.ndof) || al(&w.r0, w.ndof) || al(&w.dinv, w.ndof) ||
       al(&w.ub, (long)c->dim * c->n_nodes) || al(&w.phib, c->n_nodes) ||
-      al(&w.part, 4 * kRedBlocks) || al(&w.scal, S_NSLOTS) || al(&w.cpart, 5L * kCoopMaxBlocks) ||
-      al(&w.cscal, 4) || al(&w.p1, w.ndof) ||
+      al(&w.part, 4 * kRedBlocks) || al(&w.scal, S_NSLOTS) ||
       hipMalloc((void**)&w.mask, std::max(w.ndof, 1L)) ||
       hipHostMalloc((void**)&w.hscal, sizeof(double) * S_NSLOTS, 0)) {
     c->err = "device allocation for the Newton workspace failed";
@@ -742,6 +585,21 @@ int dot2(gedmg_ctx* c, Work& w, const double* a, const double* b, const double* 
   return GEDMG_OK;
 }
 
+int read_scalars(gedmg_ctx* c, Work& w);
+
+// a . b (and c . d when c is given) over all dofs, read back to the host.
+int dots(gedmg_ctx* c, Work& w, const double* a, const double* b, const double* c2, const double* d2, double* ab,
+         double* cd) {
+  hipLaunchKernelGGL(dot2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, a, b, c2, d2, w.ndof, w.part);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_TT, c2 ? S_TS : -1);
+  GH(hipGetLastError());
+  const int rc = read_scalars(c, w);
+  if (rc) return rc;
+  *ab = w.hscal[S_TT];
+  if (cd) *cd = w.hscal[S_TS];
+  return GEDMG_OK;
+}
+
 int read_scalars(gedmg_ctx* c, Work& w) {
   GH(hipMemcpyAsync(w.hscal, w.scal, sizeof(double) * S_NSLOTS, hipMemcpyDeviceToHost, c->stream));
   GH(hipStreamSynchronize(c->stream));
@@ -752,12 +610,12 @@ int read_scalars(gedmg_ctx* c, Work& w) {
 // Jacobi on non-positive curvature).  K is the masked matrix and w.mask the
 // Dirichlet mask of this solve.  Returns iterations in *its.
 // CG in three launches per iteration (the sparse product with partials of
-// p.q, the update, the p update), for systems large enough that the sparse
-// product, not launch latency, sets the pace; the host polls the residual
-// adaptively (each poll stalls the stream, so the next one is placed at 70 % of
-// the iterations that the observed decay rate still needs, 8 to 128 ahead).
-// Sets *curvature on non-positive curvature; w.hscal[3] receives b.b.
-int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int* its, bool* curvature) {
+// p.q, the update, the p update); the host polls the residual adaptively (each
+// poll stalls the stream, so the next one is placed at 70 % of the iterations
+// that the observed decay rate still needs, 8 to 128 ahead).
+// Sets *curvature on non-positive curvature; *bb_out receives b.b.
+int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int* its, bool* curvature,
+             double* bb_out) {
   const long n = w.ndof;
   const int gr = kRedBlocks;
   const int nd = c->dim + 1;
@@ -776,7 +634,7 @@ int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, in
   GH(hipGetLastError());
   if ((rc = read_scalars(c, w))) return rc;
   const double bb = w.hscal[S_RR];
-  w.hscal[3] = bb;
+  *bb_out = bb;
   if (bb == 0.0) return GEDMG_OK;
   if (!std::isfinite(bb)) { c->err = "non-finite right-hand side"; return GEDMG_E_NONFINITE; }
   const double tol2 = rtol * rtol * bb;
@@ -795,7 +653,6 @@ int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, in
     *its = it;
     if (it == next_poll || it == max_it) {
       if ((rc = read_scalars(c, w))) return rc;
-      w.hscal[3] = bb;
       if (w.hscal[S_FLAG] != 0.0) { *curvature = true; return GEDMG_OK; }
       const double rr = w.hscal[S_RR];
       if (!std::isfinite(rr)) { c->err = "non-finite Krylov residual"; return GEDMG_E_NONFINITE; }
@@ -819,9 +676,8 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
            int* fallbacks = nullptr) {
   const long n = w.ndof;
   const int gr = kRedBlocks;
-  const int nd = c->dim + 1;
-  const int G = c->dim == 3 ? 32 : 16;
   *its = 0;
+  double bb = 0.0;
   if (method == 1) {  // BiCGStab requested (non-symmetric tangents)
     hipLaunchKernelGGL(dot2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, w.b, w.b, nullptr, nullptr,
                        n, w.part);
@@ -829,47 +685,27 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
     GH(hipGetLastError());
     int rc0 = read_scalars(c, w);
     if (rc0) return rc0;
-    w.hscal[3] = w.hscal[S_BB];
-    if (w.hscal[3] == 0.0) {
+    bb = w.hscal[S_BB];
+    if (bb == 0.0) {
       GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
       return GEDMG_OK;
     }
-    if (!std::isfinite(w.hscal[3])) { c->err = "non-finite right-hand side"; return GEDMG_E_NONFINITE; }
-  } else if (n >= kCoopMaxDofs) {
-    bool curvature = false;
-    const int rc1 = cg_multi(c, w, K, max_it, rtol, its, &curvature);
-    if (rc1 || !curvature) return rc1;
-    if (fallbacks) ++*fallbacks;
+    if (!std::isfinite(bb)) { c->err = "non-finite right-hand side"; return GEDMG_E_NONFINITE; }
   } else {
-  // CG with the Jacobi + coarse preconditioner in one cooperative launch
-  if (w.coop_blocks == 0) {
-    int occ = 0;
-    const void* fn = G == 32 ? (const void*)cg_coop_kernel<32> : (const void*)cg_coop_kernel<16>;
-    GH(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, 0));
-    // one block per compute unit (cheaper grid barriers)
-    const int per_cu = std::max(1, std::min(occ, 1));
-    const long need = std::max(1L, (n + 255) / 256);
-    w.coop_blocks = (int)std::min<long>({(long)c->num_cu * per_cu, need, (long)kCoopMaxBlocks});
-  }
-  CoopCgArgs ca{K, c->drowptr, c->dcol, w.b, w.dinv, w.mask, w.x, w.r, w.p, w.p1, w.q, w.cpart, w.cscal,
-                n, nd, max_it, rtol * rtol};
-  void* kargs[] = {&ca};
-  const void* fn = G == 32 ? (const void*)cg_coop_kernel<32> : (const void*)cg_coop_kernel<16>;
-  GH(hipLaunchCooperativeKernel(fn, dim3(w.coop_blocks), dim3(256), kargs, 0, c->stream));
-  GH(hipMemcpyAsync(w.hscal, w.cscal, sizeof(double) * 4, hipMemcpyDeviceToHost, c->stream));
-  GH(hipStreamSynchronize(c->stream));
-  *its = (int)w.hscal[0];
-  const int cg_status = (int)w.hscal[1];
-  if (cg_status == 0) return GEDMG_OK;
-  if (cg_status == 3) { c->err = "non-finite Krylov residual"; return GEDMG_E_NONFINITE; }
-  if (cg_status == 2) { c->err = "CG reached the iteration limit"; return GEDMG_E_LINSOLVE; }
-  // non-positive curvature (the tangent is not positive definite here)
-  if (fallbacks) ++*fallbacks;
+    bool curvature = false;
+    const int rc1 = cg_multi(c, w, K, max_it, rtol, its, &curvature, &bb);
+    // CG is left for BiCGStab on non-positive curvature (the tangent is not
+    // positive definite here) and when it does not converge: while points
+    // yield with kappa below kappa_d the history enters the damage rows but,
+    // with f_d' = 0, not the displacement rows, so the tangent is not
+    // symmetric there
+    if (!(rc1 == GEDMG_E_LINSOLVE && *its >= max_it) && (rc1 || !curvature)) return rc1;
+    if (fallbacks) ++*fallbacks;
   }
   // BiCGStab from x = 0 with right Jacobi preconditioning.
   int rc;
   const int check = 8;
-  const double tol2 = rtol * rtol * w.hscal[3];  // w.hscal[3] = b.b
+  const double tol2 = rtol * rtol * bb;
   const int cg_its = *its;
   GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
   GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
@@ -1148,5 +984,219 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
     GH(hipGetLastError());
   }
   c->err = "Newton did not converge";
+  return rollback(GEDMG_E_NEWTON_NOCONV);
+}
+
+// Arc-length continuation of displacement-controlled loading (Riks; see the
+// declaration in gedmg.h): the prescribed dofs carry lambda times their unit
+// values, lambda is solved for with the fields under the constraint
+// ||Delta d||^2 + psi^2 Delta lambda^2 = ds^2, the corrector iterating in the
+// plane normal to the predictor.  Per corrector iteration: one FP64 assembly
+// (monolithic history), y = K uhat with the unmasked tangent, the masked
+// tangent, two Krylov solves a = -K_ff^-1 R_f, b = -K_ff^-1 y_f, and
+// dlambda = -(Dd . a) / (Dd . b + psi^2 Dlambda), dd = a + dlambda b.
+extern "C" int gedmg_arclength_step(gedmg_ctx* c, const gedmg_dirichlet* pattern, const gedmg_solver_opts* opts_in,
+                                    double ds, double psi, double* lambda, double* increment, double* u,
+                                    double* phi, double* kappa, const int32_t* reaction_dofs, int32_t n_reaction,
+                                    gedmg_newton_report* rep) {
+  if (!c) return GEDMG_E_ARG;
+  if (!pattern || pattern->n <= 0 || !pattern->dof || !pattern->value || !lambda || !increment || !u || !phi ||
+      !kappa || (n_reaction > 0 && !reaction_dofs) || n_reaction < 0 || !(ds > 0.0) || !(psi >= 0.0) ||
+      !std::isfinite(*lambda)) {
+    c->err = "null or inconsistent arc-length argument";
+    return GEDMG_E_ARG;
+  }
+  gedmg_solver_opts o = default_solver_opts();
+  if (opts_in) o = *opts_in;
+  if (o.max_local <= 0 || o.max_newton < 0 || o.max_krylov <= 0 || !(o.newton_rscale >= 0.0) ||
+      (o.krylov_method != 0 && o.krylov_method != 1)) {
+    c->err = "invalid solver options";
+    return GEDMG_E_ARG;
+  }
+  c->max_local = o.max_local;
+  gedmg_newton_report local{};
+  gedmg_newton_report& r = rep ? *rep : local;
+  r = gedmg_newton_report{};
+  Work* wp = nullptr;
+  int rc = ensure_work(c, &wp);
+  if (rc) return rc;
+  Work& w = *wp;
+  const long n = w.ndof, nu = (long)c->dim * c->n_nodes;
+  const int gr = kRedBlocks;
+  if (!w.al_uh) {
+    auto al = [&](double** p) { return hipMalloc((void**)p, sizeof(double) * std::max(n, 1L)); };
+    if (al(&w.al_uh) || al(&w.al_dp) || al(&w.al_a) || al(&w.al_y)) {
+      c->err = "device allocation for the arc-length workspace failed";
+      return GEDMG_E_NOMEM;
+    }
+  }
+  if (n_reaction > 0) {
+    std::vector<int32_t> rd(n_reaction);
+    GH(hipMemcpyAsync(rd.data(), reaction_dofs, sizeof(int32_t) * n_reaction, hipMemcpyDeviceToHost, c->stream));
+    GH(hipStreamSynchronize(c->stream));
+    for (int32_t d : rd)
+      if (d < 0 || d >= n) {
+        c->err = "reaction dof index out of range";
+        return GEDMG_E_ARG;
+      }
+  }
+  // Dirichlet mask (with the range check of the pattern) and the unit pattern
+  GH(hipMemsetAsync(w.mask, 0, n, c->stream));
+  GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
+  hipLaunchKernelGGL(set_mask_kernel, dim3((pattern->n + 255) / 256), dim3(256), 0, c->stream, pattern->dof,
+                     pattern->n, n, w.mask, w.scal);
+  GH(hipGetLastError());
+  if ((rc = read_scalars(c, w))) return rc;
+  if (w.hscal[S_FLAG] != 0.0) {
+    c->err = "Dirichlet dof index out of range";
+    return GEDMG_E_ARG;
+  }
+  GH(hipMemsetAsync(w.al_uh, 0, sizeof(double) * n, c->stream));
+  hipLaunchKernelGGL(scatter_kernel, dim3((pattern->n + 255) / 256), dim3(256), 0, c->stream, w.al_uh, pattern->dof,
+                     pattern->value, pattern->n);
+  // previous increment's load-factor part (host) for the orientation of the predictor
+  double prev_dlam = 0.0;
+  GH(hipMemcpyAsync(&prev_dlam, increment + n, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  GH(hipMemcpyAsync(w.ub, u, sizeof(double) * nu, hipMemcpyDeviceToDevice, c->stream));
+  GH(hipMemcpyAsync(w.phib, phi, sizeof(double) * c->n_nodes, hipMemcpyDeviceToDevice, c->stream));
+  GH(hipStreamSynchronize(c->stream));
+  const double lam0 = *lambda;
+  auto rollback = [&](int code) {
+    (void)hipMemcpyAsync(u, w.ub, sizeof(double) * nu, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(phi, w.phib, sizeof(double) * c->n_nodes, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    *lambda = lam0;
+    r.status = code;
+    return code;
+  };
+  auto set_prescribed = [&](double lam) -> int {
+    hipLaunchKernelGGL(set_dirichlet_scaled_kernel, dim3((pattern->n + 255) / 256), dim3(256), 0, c->stream, u, phi,
+                       pattern->dof, pattern->value, lam, pattern->n, c->dim, c->n_nodes);
+    GH(hipGetLastError());
+    return GEDMG_OK;
+  };
+  // assembly with the masked tangent, b = -R_f (res^2 returned) and y = K uhat
+  auto assemble_step = [&](double* res2) -> int {
+    int e;
+    if ((e = gedmg_assemble(c, u, phi, kappa, GEDMG_FP64, w.R, w.K, w.kt))) return e;
+    if ((e = spmv(c, w, w.K, w.al_uh, w.al_y, nullptr, -1))) return e;
+    hipLaunchKernelGGL(rhs_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.R, w.mask, w.b, n, w.part);
+    GH(hipGetLastError());
+    *res2 = sum_partials_host(c, w, &e);
+    if (e) return e;
+    if ((e = gedmg_status(c))) return e;
+    hipLaunchKernelGGL(mask_matrix_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, w.K, c->drowptr, c->dcol,
+                       w.mask, w.dinv, n);
+    GH(hipGetLastError());
+    return GEDMG_OK;
+  };
+  auto solve_into = [&](double* dst, double eta) -> int {
+    int its = 0;
+    const int e = krylov(c, w, w.K, o.max_krylov, eta, &its, o.krylov_method, &r.krylov_fallbacks);
+    r.krylov_iters_total += its;
+    if (e) return e;
+    GH(hipMemcpyAsync(dst, w.x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    return GEDMG_OK;
+  };
+
+  // ---- predictor.  After a first increment: the previous increment scaled to
+  // ds (secant).  First increment (zero previous increment): the path tangent
+  // t = -K_ff^-1 K_fp uhat with the history held at kappa_n, scaled to ds,
+  // forward.  At a converged state the yielded points lie on the yield surface
+  // to rounding, so a loading / elastic tangent there would be chosen by
+  // rounding; neither predictor depends on that choice.
+  if ((rc = set_prescribed(lam0))) return rollback(rc);
+  double res2 = 0.0;
+  double pp = 0.0;
+  if ((rc = dots(c, w, increment, increment, nullptr, nullptr, &pp, nullptr))) return rollback(rc);
+  const double prev_len2 = pp + psi * psi * prev_dlam * prev_dlam;
+  double dlam_p = 0.0;
+  if (prev_len2 > 0.0 && std::isfinite(prev_len2)) {
+    const double scale = ds / std::sqrt(prev_len2);
+    // al_dp = scale * previous increment (zero on the Dirichlet rows it was taken on)
+    hipLaunchKernelGGL(scale_copy_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, w.al_dp, scale, increment,
+                       n);
+    GH(hipGetLastError());
+    dlam_p = scale * prev_dlam;
+  } else {
+    {
+      struct Hold {
+        gedmg_ctx* c;
+        ~Hold() { c->frozen_history = 0; }
+      } hold{c};
+      c->frozen_history = 1;
+      if ((rc = assemble_step(&res2))) return rollback(rc);
+    }
+    hipLaunchKernelGGL(masked_neg_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, w.al_y, w.mask, w.b, n);
+    GH(hipGetLastError());
+    if ((rc = solve_into(w.al_dp, o.krylov_rtol))) return rollback(rc);
+    double tt = 0.0;
+    if ((rc = dots(c, w, w.al_dp, w.al_dp, nullptr, nullptr, &tt, nullptr))) return rollback(rc);
+    dlam_p = ds / std::sqrt(tt + psi * psi);
+    hipLaunchKernelGGL(axpy_scalar_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, w.al_dp, dlam_p - 1.0,
+                       w.al_dp, n);  // al_dp = dlam_p * t
+    GH(hipGetLastError());
+  }
+  hipLaunchKernelGGL(update_fields_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, u, phi, w.al_dp, c->dim,
+                     c->n_nodes);
+  GH(hipGetLastError());
+  double lam = lam0 + dlam_p;
+  if ((rc = set_prescribed(lam))) return rollback(rc);
+
+  // ---- corrector in the normal plane
+  double res0 = -1.0;
+  for (int it = 0; it <= o.max_newton; ++it) {
+    if ((rc = assemble_step(&res2))) return rollback(rc);
+    const double res = std::sqrt(res2);
+    if (it < 32) r.res_norm[it] = res;
+    r.newton_iters = it;
+    if (!std::isfinite(res)) { c->err = "non-finite residual"; return rollback(GEDMG_E_NONFINITE); }
+    if (res0 < 0.0) res0 = res;
+    if (res <= std::max(o.newton_rtol * std::max(o.newton_rscale, res0), o.newton_atol)) {
+      GH(hipMemcpyAsync(w.ktmp, kappa, sizeof(double) * w.nq, hipMemcpyDeviceToDevice, c->stream));
+      GH(hipMemcpyAsync(kappa, w.kt, sizeof(double) * w.nq, hipMemcpyDeviceToDevice, c->stream));
+      hipLaunchKernelGGL(count_growth_kernel, dim3(gr), dim3(kThreads), 0, c->stream, kappa, w.ktmp, w.nq, w.part);
+      GH(hipGetLastError());
+      r.n_yielded_qp = (int)sum_partials_host(c, w, &rc);
+      if (rc) return rc;
+      if (n_reaction > 0) {
+        hipLaunchKernelGGL(gather_sum_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.R, reaction_dofs, n_reaction,
+                           n, w.part);
+        GH(hipGetLastError());
+        r.reaction = sum_partials_host(c, w, &rc);
+        if (rc) return rc;
+      }
+      hipLaunchKernelGGL(field_increment_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, u, phi, w.ub,
+                         w.phib, w.mask, increment, c->dim, c->n_nodes);
+      const double dlam = lam - lam0;
+      GH(hipMemcpyAsync(increment + n, &dlam, sizeof(double), hipMemcpyHostToDevice, c->stream));
+      GH(hipStreamSynchronize(c->stream));
+      *lambda = lam;
+      r.status = GEDMG_OK;
+      return GEDMG_OK;
+    }
+    if (it == o.max_newton) break;
+    const double eta =
+        o.krylov_forcing ? std::max(o.krylov_rtol, std::min(1e-3, res / std::max(res0, 1e-300))) : o.krylov_rtol;
+    if ((rc = solve_into(w.al_a, eta))) return rollback(rc);  // a = -K_ff^-1 R_f (w.b holds -R_f)
+    hipLaunchKernelGGL(masked_neg_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, w.al_y, w.mask, w.b, n);
+    GH(hipGetLastError());
+    int its = 0;
+    rc = krylov(c, w, w.K, o.max_krylov, eta, &its, o.krylov_method, &r.krylov_fallbacks);  // b in w.x
+    r.krylov_iters_total += its;
+    if (rc) return rollback(rc);
+    double da = 0.0, db = 0.0;
+    if ((rc = dots(c, w, w.al_dp, w.al_a, w.al_dp, w.x, &da, &db))) return rollback(rc);
+    const double den = db + psi * psi * dlam_p;
+    if (!(std::fabs(den) > 0.0)) { c->err = "arc-length corrector breakdown"; return rollback(GEDMG_E_LINSOLVE); }
+    const double dl = -da / den;
+    hipLaunchKernelGGL(axpy_scalar_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, w.al_a, dl, w.x, n);
+    hipLaunchKernelGGL(update_fields_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, u, phi, w.al_a, c->dim,
+                       c->n_nodes);
+    GH(hipGetLastError());
+    lam += dl;
+    if ((rc = set_prescribed(lam))) return rollback(rc);
+  }
+  c->err = "arc-length corrector did not converge";
   return rollback(GEDMG_E_NEWTON_NOCONV);
 }

@@ -131,12 +131,16 @@ def lib():
         if hasattr(L, "gedmg_newton_step"):
             L.gedmg_newton_step.argtypes = [vp, C.POINTER(Dirichlet), C.POINTER(SolverOpts), C.c_int,
                                             vp, vp, vp, vp, vp, i32, C.POINTER(NewtonReport)]
+        if hasattr(L, "gedmg_arclength_step"):
+            L.gedmg_arclength_step.argtypes = [vp, C.POINTER(Dirichlet), C.POINTER(SolverOpts), dp, dp,
+                                               C.POINTER(dp), vp, vp, vp, vp, vp, i32, C.POINTER(NewtonReport)]
         if hasattr(L, "gedmg_adjoint"):
             L.gedmg_adjoint.argtypes = [vp, i32, C.POINTER(Dirichlet), vp, vp, i32, vp, i32,
                                         C.POINTER(SolverOpts), vp, vp, vp, C.POINTER(dp), C.POINTER(dp),
                                         C.POINTER(dp), C.POINTER(AdjointReport)]
         for name in ("gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
-                     "gedmg_assemble", "gedmg_assemble_static", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
+                     "gedmg_assemble", "gedmg_assemble_static", "gedmg_status", "gedmg_newton_step",
+                     "gedmg_arclength_step", "gedmg_adjoint",
                      "gedmg_energy_jet", "gedmg_profile", "gedmg_profile_read", "gedmg_probe_mfma"):
             if hasattr(L, name):
                 getattr(L, name).restype = C.c_int
@@ -147,7 +151,8 @@ def lib():
 STATIC_MAX_QP = 262144  # GEDMG_STATIC_MAX_QP
 
 EXPORTED = ("gedmg_last_error", "gedmg_create", "gedmg_destroy", "gedmg_set_params", "gedmg_csr",
-            "gedmg_assemble", "gedmg_assemble_static", "gedmg_status", "gedmg_newton_step", "gedmg_adjoint",
+            "gedmg_assemble", "gedmg_assemble_static", "gedmg_status", "gedmg_newton_step",
+            "gedmg_arclength_step", "gedmg_adjoint",
             "gedmg_energy_jet", "gedmg_profile", "gedmg_profile_read", "gedmg_probe_mfma")
 
 
@@ -367,6 +372,36 @@ class Context:
         if rc != 0 and raise_on_error:
             self._check(rc)
         return out
+
+    def arclength_step(self, u, phi, kappa, pattern_dofs, pattern_unit, lam, increment, ds, psi=1.0,
+                       reaction_dofs=None, raise_on_error=True, **solver):
+        """One arc-length increment in place on (u, phi, kappa) and the device
+        array increment [ndof + 1] (gedmg_arclength_step).  Returns (lambda,
+        report dict)."""
+        self._check_fields(u, phi, kappa)
+        _check_array(increment, self.ndof + 1, self.dev, "increment")
+        dofs = _dof_index_array(pattern_dofs, self.ndof, self.dev, "pattern_dofs")
+        vals = _f64(pattern_unit, self.dev).reshape(-1)
+        if vals.numel() != dofs.numel() or dofs.numel() == 0:
+            raise GedmgError(-1, "one unit value per prescribed dof, at least one dof")
+        pat = Dirichlet(int(dofs.numel()), C.c_void_p(dofs.data_ptr()), C.c_void_p(vals.data_ptr()))
+        opts = solver_opts(**solver)
+        rd = None
+        nr = 0
+        if reaction_dofs is not None:
+            rd = _dof_index_array(reaction_dofs, self.ndof, self.dev, "reaction_dofs")
+            nr = int(rd.numel())
+        lamc = C.c_double(float(lam))
+        rep = NewtonReport()
+        rc = lib().gedmg_arclength_step(self._h, C.byref(pat), C.byref(opts), float(ds), float(psi), C.byref(lamc),
+                                        _dptr(increment), _dptr(u), _dptr(phi), _dptr(kappa), _dptr(rd), nr,
+                                        C.byref(rep))
+        out = dict(status=rc, newton_iters=rep.newton_iters, krylov_iters=rep.krylov_iters_total,
+                   n_yielded_qp=rep.n_yielded_qp, reaction=rep.reaction, krylov_fallbacks=rep.krylov_fallbacks,
+                   res_norm=list(rep.res_norm[: min(rep.newton_iters + 1, 32)]))
+        if rc != 0 and raise_on_error:
+            self._check(rc)
+        return lamc.value, out
 
     def adjoint(self, path, checkpoint_every=5):
         """Loss and raw-parameter gradients of a load path (see LoadPath).

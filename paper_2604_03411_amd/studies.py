@@ -1,14 +1,17 @@
 """Load-path studies of the paper run through the gedmg library.
 
 These are drivers: they build the seeded study inputs (workloads), call
-gedmg_newton_step once per load increment and collect what the paper tracks.
+gedmg_newton_step (or gedmg_arclength_step) once per load increment and
+collect what the paper tracks.
 Every step of the method runs in the HIP library; the drivers only read back
 scalars (reaction, the largest history value) between increments.
 
 * single_element: Sec. 5.1, one 1 x 1 x 1 mm Hex8 element of the closed-form
   model (compressible Neo-Hooke, G = identity) under uniaxial tension to
-  0.5 mm, local model, for a set of (eta_d, kappa_d).  Tracks the nominal
-  axial stress, kappa and d = 1 - f_d(kappa) against the stretch.
+  0.5 mm, local model, for a set of (eta_d, kappa_d), by arc-length
+  continuation (gedmg_arclength_step) or staggered displacement steps.
+  Tracks the nominal axial stress, kappa and d = 1 - f_d(kappa) against the
+  stretch.
 * uniform_plate: Sec. 5.2, the 10 x 10 x 1 mm plate under uniaxial tension in
   equal increments, with the local model (history updated after each step) or
   the gradient-enhanced model under the monolithic or the staggered scheme, on
@@ -53,26 +56,41 @@ def damage(kappa_max, mat):
     return 1.0 - math.exp(-mat["eta_d"] * max(kappa_max - mat["kappa_d"], 0.0))
 
 
-def single_element(eta_d, kappa_d, n_steps=50, total_disp=0.5):
+def single_element(eta_d, kappa_d, n_steps=50, total_disp=0.5, method="arclength", ds=0.02):
+    """method "arclength": Riks increments of length ds on the displacement
+    of the loaded face (the continuation the paper uses for this study);
+    "staggered": n_steps equal displacement increments with the history
+    updated after each converged step."""
     case = W.single_element_case(eta_d=eta_d, kappa_d=kappa_d, n_steps=n_steps, total_disp=total_disp)
     ctx = G.Context.from_case(case)
     u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
-    du = W.uniaxial_increment(case)
     rd = W.reaction_dofs(case)
     rows = []
-    for n in range(1, n_steps + 1):
-        bd, bv = W.symmetric_tension_bc(case, n)
-        rep = ctx.newton_step(u, phi, kap, bd, bv, reaction_dofs=rd, predictor_du=du, scheme="staggered",
-                              **RELATIVE)
-        k = float(kap.max())
-        # nominal stress: reaction over the reference area (1 mm^2), with the
-        # history of the converged step (the global solve used kappa_{n-1})
-        fd_prev = 1.0 - damage(rows[-1]["kappa"], case.material) if rows else 1.0
-        p11 = rep["reaction"] / fd_prev * (1.0 - damage(k, case.material)) if fd_prev > 0.0 else 0.0
-        rows.append(dict(stretch=1.0 + total_disp * n / n_steps, kappa=k, d=damage(k, case.material), P11=p11,
-                         newton_iters=rep["newton_iters"]))
+    if method == "arclength":
+        bd, bu = W.arclength_pattern(case, W.symmetric_tension_bc)
+        inc = torch.zeros(ctx.ndof + 1, dtype=torch.float64, device=ctx.dev)
+        lam = 0.0
+        while lam < total_disp:
+            lam, rep = ctx.arclength_step(u, phi, kap, bd, bu, lam, inc, ds, 1.0, reaction_dofs=rd,
+                                          newton_rtol=1e-9, newton_atol=0.0, newton_rscale=0.0, krylov_rtol=1e-14)
+            k = float(kap.max())
+            # nominal stress: the reaction on the unit face
+            rows.append(dict(stretch=1.0 + lam, kappa=k, d=damage(k, case.material), P11=rep["reaction"],
+                             newton_iters=rep["newton_iters"]))
+    else:
+        du = W.uniaxial_increment(case)
+        for n in range(1, n_steps + 1):
+            bd, bv = W.symmetric_tension_bc(case, n)
+            rep = ctx.newton_step(u, phi, kap, bd, bv, reaction_dofs=rd, predictor_du=du, scheme="staggered",
+                                  **RELATIVE)
+            k = float(kap.max())
+            # the global solve used kappa_{n-1}: rescale to the updated history
+            fd_prev = 1.0 - damage(rows[-1]["kappa"], case.material) if rows else 1.0
+            p11 = rep["reaction"] / fd_prev * (1.0 - damage(k, case.material)) if fd_prev > 0.0 else 0.0
+            rows.append(dict(stretch=1.0 + total_disp * n / n_steps, kappa=k, d=damage(k, case.material), P11=p11,
+                             newton_iters=rep["newton_iters"]))
     ctx.close()
-    return dict(study="single_element", eta_d=eta_d, kappa_d=kappa_d, steps=rows)
+    return dict(study="single_element", method=method, eta_d=eta_d, kappa_d=kappa_d, steps=rows)
 
 
 def uniform_plate(mesh_kind="coarse", model="nonlocal", scheme="monolithic", n_steps=1000, total_disp=80.0,
@@ -154,6 +172,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--total", type=float, default=None)
     ap.add_argument("--every", type=int, default=1, help="keep every k-th step in the output")
+    ap.add_argument("--method", choices=["arclength", "staggered"], default="arclength",
+                    help="single-element continuation")
     args = ap.parse_args()
     torch.cuda.set_device(0)
     if args.study == "train":
@@ -162,7 +182,7 @@ def main():
         return
     if args.study == "single-element":
         for eta, kd in ((1.0, 1.0), (10.0, 1.0), (100.0, 1.0), (10.0, 0.0), (10.0, 2.0)):
-            r = single_element(eta, kd, args.steps or 50, args.total or 0.5)
+            r = single_element(eta, kd, args.steps or 50, args.total or 0.5, args.method)
             r["steps"] = r["steps"][::args.every]
             print(json.dumps(r), flush=True)
         return

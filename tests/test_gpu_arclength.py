@@ -1,0 +1,93 @@
+"""Arc-length continuation on the GPU (gedmg_arclength_step) against the
+oracle's Riks increments.
+
+* The single-element study of Sec. 5.1 (closed-form local model, eta_d = 10,
+  kappa_d = 1): the path rises to the peak force and follows the softening
+  branch until the force is below 1e-3 of the peak, to 0.5 mm.  The oracle's
+  increments are pinned to the closed-form uniaxial path on the CPU.
+* The necked Q4 strip of 20 elements (gradient-enhanced closed-form model,
+  eta_d = 2): 60 increments.  Past the force maximum the damage localises in
+  the neck while the rest of the strip unloads, and the end displacement
+  falls with the force (snap-back) before it grows again: a path that
+  displacement control cannot follow.
+
+Every increment's load factor, reaction and state match the oracle's."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fem, solve
+
+from gpu_common import rel_err, sync
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_path(case, bd, bu, ds, n_max, lam_end, **kw):
+    m = fem.Model(case)
+    rd = W.reaction_dofs(case)
+    d = fem.dof_vector(case.u, case.phi)
+    kap = case.kappa.copy()
+    lam, prev, ref = 0.0, None, []
+    while len(ref) < n_max and lam < lam_end:
+        d, lam, kt, inc, hist, ok = solve.arclength_step(m, case.mesh, d, lam, kap, bd, bu, ds, prev=prev, **kw)
+        assert ok, len(ref)
+        R, _, _ = fem.assemble(m, case.mesh, d, kap, tangent=False)
+        kap, prev = kt, inc
+        ref.append((lam, d.copy(), kt.copy(), solve.reaction(R, rd)))
+    return ref
+
+
+def _gpu_follow(G, case, bd, bu, ds, ref, lam_tol, state_tol, reaction_tol, **solver):
+    ctx = G.Context.from_case(case)
+    rd = W.reaction_dofs(case)
+    u, phi, kg = ctx.fields(case.u, case.phi, case.kappa)
+    inc = torch.zeros(ctx.ndof + 1, dtype=torch.float64, device=ctx.dev)
+    lam, out = 0.0, []
+    for n, (lo, do, ko, ro) in enumerate(ref):
+        lam, rep = ctx.arclength_step(u, phi, kg, bd, bu, lam, inc, ds, 1.0, reaction_dofs=rd, **solver)
+        sync()
+        uo, po = fem.split_dofs(do, case.mesh.dim)
+        print(f"  increment {n}: lambda gpu {lam:.12f} oracle {lo:.12f}; reaction gpu {rep['reaction']:.10e} "
+              f"oracle {ro:.10e}; iterations {rep['newton_iters']}", flush=True)
+        assert abs(lam - lo) <= lam_tol * abs(lo)
+        assert abs(rep["reaction"] - ro) <= reaction_tol * abs(ro)
+        assert rel_err(u.cpu().numpy(), uo) <= state_tol
+        assert rel_err(kg.cpu().numpy(), ko) <= state_tol
+        out.append(rep["reaction"])
+    ctx.close()
+    return np.array(out)
+
+
+def test_single_element_softening_path_matches_oracle():
+    from paper_2604_03411_amd import gedmg as G
+    case = W.single_element_case(eta_d=10.0, kappa_d=1.0)
+    bd, bu = W.arclength_pattern(case, W.symmetric_tension_bc)
+    print("[arc-length] single Hex8 element, eta_d 10, kappa_d 1, ds 0.02 to 0.5 mm", flush=True)
+    rel = dict(rtol=1e-9, atol=0.0, rscale=0.0)
+    ref = _oracle_path(case, bd, bu, 0.02, 60, 0.5, **rel)
+    f = _gpu_follow(G, case, bd, bu, 0.02, ref, 1e-10, 1e-10, 1e-8, newton_rtol=1e-9, newton_atol=0.0,
+                    newton_rscale=0.0, krylov_rtol=1e-14)
+    k = int(f.argmax())
+    assert 0 < k < len(f) - 1 and f[-1] < 1e-3 * f[k]
+
+
+def test_strip_snap_back_matches_oracle():
+    from paper_2604_03411_amd import gedmg as G
+    case = W.strip_case(nx=20)
+    bd, bu = W.arclength_pattern(case)
+    print("[arc-length] necked Q4 strip 20x1, ds 0.1, 60 increments", flush=True)
+    atol = 1e-11
+    ref = _oracle_path(case, bd, bu, 0.1, 60, np.inf, atol=atol)
+    # the strip yields below kappa_d at first, where the tangent is not symmetric
+    f = _gpu_follow(G, case, bd, bu, 0.1, ref, 1e-8, 1e-7, 1e-7, newton_rtol=0.0, newton_atol=atol,
+                    krylov_rtol=1e-13, krylov_method="bicgstab")
+    lam = np.array([r[0] for r in ref])
+    k = int(f.argmax())
+    assert 0 < k < len(f) - 1  # the force passes its maximum
+    dl = np.diff(lam[k:])
+    # snap-back: the load factor falls over several increments after the peak,
+    # then grows again while the force keeps falling
+    assert (dl < 0.0).sum() >= 5 and dl[-1] > 0.0
+    assert (np.diff(f[k:]) < 0.0).all()
