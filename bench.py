@@ -212,6 +212,9 @@ def bench_adjoint(G, W, torch, checkpoint_every=5):
     dt = time.perf_counter() - t0
     ctx.close()
     return dict(workload=case.name, elements=case.mesh.n_elems, steps=steps, checkpoint_every=checkpoint_every,
+                total_disp=case.extra["total_disp"],
+                total_disp_note="the path stops at 0.125 (not 0.25): past the seeded networks' limit point "
+                                "near 16 % strain displacement control has no unique converged state",
                 n_params=int(ge.size + gy.size), s_per_step=dt / steps, total_s=dt, loss=loss,
                 forward_s=rep["t_forward_s"], recompute_s=rep["t_recompute_s"], reverse_s=rep["t_reverse_s"],
                 newton_iters=rep["newton_iters_total"], krylov_iters=rep["krylov_iters_total"])
@@ -343,7 +346,8 @@ def main():
     if args.copy_probe:
         copy_probe(torch)
     if args.mfma_probe:
-        n = G.probe_mfma(4 * 256, 4000)
+        # many short blocks, so that every SIMD gets the same share of the work
+        n = G.probe_mfma(64 * 256, 250)
         log(f"mfma probe: {n} FP64 16x16x4 products ({n * 2048 / 1e9:.1f} GFLOP)")
     case = W.make_case(4)
     mesh = case.mesh
@@ -407,7 +411,9 @@ def main():
         scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
         config=dict(workload=case.name, elements=mesh.n_elems, qp=nq, dofs=int(mesh.ndof), nnz=int(ctx.nnz),
                     energy_net=f"3-{H}x{L}-1", yield_net=f"1-{case.yield_.width}x{case.yield_.n_hidden}-1",
-                    precision="fp64"),
+                    precision="fp64", mu_e=case.material["mu_e"],
+                    mu_e_rule="initial shear modulus of psi_e = E / (2 (1 + nu)), E = 210, nu = 0.3",
+                    energy_monotone_mask=case.energy.monotone_mask),
         phases_ms=dict(inputs=in_ms, jets=jet_ms, history=hist_ms, elements=elem_ms, fills=fill_ms,
                        dominant="energy_jet" if jet_ms >= elem_ms else "element"),
         roofline=roofline, element_roofline=element_roofline, cpu_baseline=cpu, **extra)

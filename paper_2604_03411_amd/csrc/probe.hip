@@ -1,8 +1,9 @@
 // Calibration probe for the matrix-core counters: a kernel that issues only
-// FP64 16x16x4 matrix products (4 independent accumulation chains per wave, one
-// wave per SIMD), so that the MFMA-busy counter of a profiled run can be
+// FP64 16x16x4 matrix products (4 independent accumulation chains per wave,
+// 4 waves per block), so that the MFMA-busy counter of a profiled run can be
 // related to a known number of products, as a device copy of known size
-// relates the byte counters to bytes.
+// relates the byte counters to bytes.  Launched as many short blocks, so that
+// the dispatcher's uneven placement of blocks on compute units averages out.
 #include "gedmg_internal.h"
 
 namespace gedmg {

@@ -136,3 +136,70 @@ def test_library_rejects_out_of_range_reaction_dofs(G):
     assert rc == E_ARG
     assert torch.equal(u, u0)
     ctx.close()
+
+
+def _homogeneous_state(case, stretch):
+    """u of the homogeneous deformation diag(s, 0.99 / sqrt(s), 1.01 / sqrt(s))
+    on the unit cube (nearly isochoric), phi = 0."""
+    X = case.mesh.X
+    t = 1.0 / np.sqrt(stretch)
+    u = np.stack([(stretch - 1.0) * X[0], (0.99 * t - 1.0) * X[1], (1.01 * t - 1.0) * X[2]])
+    return u, np.zeros(case.mesh.n_nodes)
+
+
+def test_history_tie_on_the_yield_surface(G):
+    """kappa_n equal to the driving force (h(kappa_n) = 0 up to rounding) at
+    every point of one homogeneously stretched element of the closed-form
+    local model, above kappa_d.  Whether such a point counts as loading is
+    decided by rounding, so R and kappa_trial must match the oracle while K
+    must equal either the oracle's loading tangent or its elastic one (taken
+    with kappa_n moved by 1e-13 relative to either side), which differ here."""
+    case = W.single_element_case(eta_d=10.0, kappa_d=0.1)
+    u, phi = _homogeneous_state(case, 1.2)
+    m = fem.Model(case)
+    d = fem.dof_vector(u, phi)
+    _, _, psi = fem.assemble(m, case.mesh, d, np.zeros_like(case.kappa), tangent=False)
+    kap = psi.copy()  # local model: the updated history is psi_NH itself
+    assert kap.min() > 0.1 and np.ptp(kap) <= 1e-14 * kap.max()
+    print(f"[edge] history tie at kappa_n = psi_NH = {kap.max():.6f}", flush=True)
+    R0, _, k0 = fem.assemble(m, case.mesh, d, kap)
+    _, K_load, _ = fem.assemble(m, case.mesh, d, kap * (1.0 - 1e-13))
+    _, K_el, _ = fem.assemble(m, case.mesh, d, kap * (1.0 + 1e-13))
+    assert rel_err(K_load.data, K_el.data) > 1e-3
+    ctx = G.Context.from_case(case)
+    R, K, kt = ctx.assemble(*ctx.fields(u, phi, kap), "fp64")
+    sync()
+    assert ctx.status() == 0
+    Kg = to_scipy(ctx, K).data
+    assert rel_err(R.cpu().numpy(), R0) <= 1e-12
+    assert rel_err(kt.cpu().numpy(), k0) <= 1e-12
+    e_load, e_el = rel_err(Kg, K_load.data), rel_err(Kg, K_el.data)
+    print(f"  K against the loading tangent {e_load:.2e}, against the elastic one {e_el:.2e}", flush=True)
+    assert min(e_load, e_el) <= 1e-11
+    ctx.close()
+
+
+def test_history_at_kappa_d(G):
+    """kappa_n exactly kappa_d at every point: elastic points (psi_NH below
+    kappa_d) keep f_d = 1, so R is the undamaged response; points stretched
+    past kappa_d yield from the kink of the degradation function.  Both
+    against the oracle at 1e-12."""
+    for stretch, yields in ((1.05, False), (1.2, True)):
+        case = W.single_element_case(eta_d=10.0, kappa_d=0.3)
+        u, phi = _homogeneous_state(case, stretch)
+        kap = np.full_like(case.kappa, 0.3)
+        m = fem.Model(case)
+        d = fem.dof_vector(u, phi)
+        R0, K0, k0 = fem.assemble(m, case.mesh, d, kap)
+        assert bool((k0 > 0.3).all()) == yields and bool((k0 == 0.3).all()) != yields
+        print(f"[edge] kappa_n = kappa_d, stretch {stretch}: yields {yields}", flush=True)
+        ctx = G.Context.from_case(case)
+        R, K, kt = ctx.assemble(*ctx.fields(u, phi, kap), "fp64")
+        sync()
+        assert ctx.status() == 0
+        assert rel_err(R.cpu().numpy(), R0) <= 1e-12
+        assert rel_err(to_scipy(ctx, K).data, K0.data) <= 1e-12
+        assert rel_err(kt.cpu().numpy(), k0) <= 1e-12
+        if not yields:
+            assert np.array_equal(kt.cpu().numpy(), kap)
+        ctx.close()
