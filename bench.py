@@ -23,7 +23,8 @@ Also reported on the same line:
     cores over a bounded sample of the headline workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-mixed] [--no-adjoint] [--copy-probe]
+                       [--no-mixed] [--no-mixed-paths] [--no-cube-newton] [--no-adjoint]
+                       [--copy-probe] [--mfma-probe]
 """
 from __future__ import annotations
 
@@ -149,7 +150,7 @@ def cube_converged(G, W, torch, case, precision):
                         backtracks=rep["backtracks"], krylov_fallbacks=rep["krylov_fallbacks"])
 
 
-def bench_mixed(G, W, torch, ctx, fields, out, ref, steps, warmup, nq, case=None, cube_newton=True):
+def bench_mixed(G, W, torch, ctx, fields, out, ref, steps, warmup, nq, case=None, cube_newton=True, paths=True):
     res = {}
     cube_ref = None
     if cube_newton:
@@ -168,8 +169,9 @@ def bench_mixed(G, W, torch, ctx, fields, out, ref, steps, warmup, nq, case=None
         R, K, _ = out
         errs = dict(residual=rel_err(R, ref[0]), tangent=rel_err(K, ref[1]))
         log(f"{prec}: {ms / steps:.3f} ms/step, residual err {errs['residual']:.2e} "
-            f"tangent err {errs['tangent']:.2e}; converged-displacement check")
-        errs.update(mixed_newton_error(G, W, torch, prec))
+            f"tangent err {errs['tangent']:.2e}" + ("; converged-displacement check" if paths else ""))
+        if paths:
+            errs.update(mixed_newton_error(G, W, torch, prec))
         if cube_ref is not None:
             u1, p1, info = cube_converged(G, W, torch, sub, prec)
             info.update(displacement=rel_err(u1, cube_ref[0]), phi=rel_err(p1, cube_ref[1]),
@@ -326,6 +328,8 @@ def main():
                     help="elements of the oracle sample timed on one thread")
     ap.add_argument("--no-cube-newton", action="store_true",
                     help="skip the converged-displacement solves of the heterogeneous sub-cube")
+    ap.add_argument("--no-mixed-paths", action="store_true",
+                    help="skip the mixed-precision load paths (assembly timing and errors only; for counter runs)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
@@ -389,7 +393,7 @@ def main():
     if not args.no_mixed:
         ref = (out[0].clone(), out[1].clone())
         extra["mixed"] = bench_mixed(G, W, torch, ctx, fields, out, ref, args.steps, args.warmup, nq, case,
-                                     not args.no_cube_newton)
+                                     not (args.no_cube_newton or args.no_mixed_paths), not args.no_mixed_paths)
         del ref
     ctx.close()
     del out, fields
