@@ -81,3 +81,21 @@ def test_adjoint_rejects_bad_reaction_dofs_and_targets():
     expect_arg_error(lambda: ctx.adjoint(bad))
     short = G.LoadPath(u, phi, kap, bcs, [1], [0.0])
     expect_arg_error(lambda: ctx.adjoint(short))
+
+
+def test_arclength_step_rejects_malformed_arrays():
+    ctx = stub()
+    u, phi, kap = fields(ctx)
+    inc = torch.zeros(ctx.ndof + 1, dtype=torch.float64)
+    ok = dict(pattern_dofs=[0, 3], pattern_unit=[0.0, 1.0], lam=0.0, ds=0.1)
+    # increment of the wrong size or type
+    expect_arg_error(lambda: ctx.arclength_step(u, phi, kap, increment=inc[:-1], **ok))
+    expect_arg_error(lambda: ctx.arclength_step(u, phi, kap, increment=inc.float(), **ok))
+    # pattern out of range, or values not matching the dofs, or empty
+    expect_arg_error(lambda: ctx.arclength_step(u, phi, kap, [ctx.ndof], [1.0], 0.0, inc, 0.1))
+    expect_arg_error(lambda: ctx.arclength_step(u, phi, kap, [0, 3], [1.0], 0.0, inc, 0.1))
+    expect_arg_error(lambda: ctx.arclength_step(u, phi, kap, [], [], 0.0, inc, 0.1))
+    # fields and reaction dofs
+    expect_arg_error(lambda: ctx.arclength_step(u[:-1], phi, kap, increment=inc, **ok))
+    expect_arg_error(lambda: ctx.arclength_step(u, phi, kap, increment=inc, reaction_dofs=[-1], **ok))
+    expect_arg_error(lambda: ctx.arclength_step(u, phi, kap, increment=inc, not_an_option=2, **ok))

@@ -203,3 +203,36 @@ def test_history_at_kappa_d(G):
         if not yields:
             assert np.array_equal(kt.cpu().numpy(), kap)
         ctx.close()
+
+
+def test_arclength_rejects_invalid_arguments(G):
+    """gedmg_arclength_step's own checks (a C caller has no binding in front):
+    non-positive arc length, negative load-factor scale, a non-finite load
+    factor, pattern dofs out of range; each GEDMG_E_ARG with u, phi and lambda
+    untouched."""
+    case = W.strip_case(nx=4)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    u0 = u.clone()
+    inc = torch.zeros(ctx.ndof + 1, dtype=torch.float64, device=ctx.dev)
+    bd, bu = W.arclength_pattern(case)
+    print("[edge] arc-length argument checks", flush=True)
+    for kw in (dict(ds=0.0, psi=1.0, lam=0.0), dict(ds=-0.1, psi=1.0, lam=0.0), dict(ds=0.1, psi=-1.0, lam=0.0),
+               dict(ds=0.1, psi=1.0, lam=float("nan"))):
+        lam, rep = ctx.arclength_step(u, phi, kap, bd, bu, kw["lam"], inc, kw["ds"], kw["psi"], raise_on_error=False)
+        sync()
+        assert rep["status"] == E_ARG, kw
+    import ctypes as C
+    dofs = torch.tensor([ctx.ndof], dtype=torch.int32, device=ctx.dev)
+    vals = torch.ones(1, dtype=torch.float64, device=ctx.dev)
+    pat = G.Dirichlet(1, C.c_void_p(dofs.data_ptr()), C.c_void_p(vals.data_ptr()))
+    lamc = C.c_double(0.25)
+    rep = G.NewtonReport()
+    opts = G.solver_opts()
+    rc = G.lib().gedmg_arclength_step(ctx._h, C.byref(pat), C.byref(opts), 0.1, 1.0, C.byref(lamc),
+                                      C.c_void_p(inc.data_ptr()), C.c_void_p(u.data_ptr()),
+                                      C.c_void_p(phi.data_ptr()), C.c_void_p(kap.data_ptr()), None, 0, C.byref(rep))
+    sync()
+    assert rc == E_ARG and lamc.value == 0.25
+    assert torch.equal(u, u0)
+    ctx.close()
