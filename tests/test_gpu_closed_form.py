@@ -7,7 +7,11 @@ scheme of Sec. 3.2, against the oracle:
   once at the converged fields) on a notched plate with the network model;
 * the single-element study of Sec. 5.1 (local model, uniaxial tension of one
   Hex8 element): kappa(stretch) does not depend on eta_d or kappa_d, and the
-  GPU path equals the oracle's."""
+  GPU path equals the oracle's;
+* the uniform-plate study of Sec. 5.2 on its coarse mesh in 30 increments of
+  1 mm, for the three combinations the paper compares (local model under the
+  staggered scheme, gradient-enhanced model monolithic and staggered): states
+  and reactions at every increment against the oracle's."""
 import dataclasses
 
 import numpy as np
@@ -138,3 +142,38 @@ def test_single_element_study_kappa_independent_of_damage_parameters():
     # ... and its onset (the first step with kappa > kappa_d) comes later with kappa_d
     onset = [int(np.argmax(kk > kd)) for kd in (0.0, 1.0, 2.0)]
     assert onset[0] < onset[1] < onset[2]
+
+
+@pytest.mark.parametrize("model,scheme", [("local", "staggered"), ("nonlocal", "monolithic"),
+                                          ("nonlocal", "staggered")])
+def test_uniform_plate_schemes_match_oracle(model, scheme):
+    from paper_2604_03411_amd import gedmg as G
+    steps, total = 30, 30.0
+    case = W.uniform_plate_case("coarse", nonlocal_=(model == "nonlocal"), n_steps=steps, total_disp=total)
+    print(f"[plate] coarse {model} {scheme}: {steps} increments to {total} mm", flush=True)
+    recs = solve.load_path(case, fem.Model(case), steps=steps, bc_fn=W.symmetric_tension_bc,
+                           predictor_fn=lambda c, u, n: u + W.uniaxial_increment(c), rtol=1e-10, scheme=scheme,
+                           rscale=0.0)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    du = W.uniaxial_increment(case)
+    rd = W.reaction_dofs(case)
+    beta, sq = case.material["beta_d"], np.sqrt(case.mesh.ndof)
+    for r in recs:
+        n = r["step"]
+        bd, bv = W.symmetric_tension_bc(case, n)
+        atol = max(1e-10, 1e-14 * beta * max(float(r["kappa_prev"].max()), 1.0) * sq)
+        rep = ctx.newton_step(u, phi, kap, bd, bv, reaction_dofs=rd, predictor_du=du, scheme=scheme,
+                              newton_rtol=1e-10, newton_atol=atol, newton_rscale=0.0, krylov_rtol=1e-13)
+        sync()
+        uo, po = fem.split_dofs(r["d"], 3)
+        ko = r["kappa"]
+        if n % 10 == 0:
+            print(f"  increment {n}: reaction gpu {rep['reaction']:.10g} oracle {r['reaction']:.10g}; "
+                  f"max kappa {float(kap.max()):.6g}", flush=True)
+        assert abs(rep["reaction"] - r["reaction"]) <= 1e-8 * abs(r["reaction"])
+        assert rel_err(u.cpu().numpy(), uo) <= 1e-8
+        assert rel_err(kap.cpu().numpy(), ko) <= 1e-6
+        if model == "nonlocal":
+            assert rel_err(phi.cpu().numpy(), po) <= 1e-6
+    ctx.close()
