@@ -47,6 +47,7 @@ JET_SOURCES = [os.path.join(CSRC, n) for n in ("icnn_jet.hip", "device_common.h"
 ELEM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_element_hex8_64cube.txt")
 ELEM_SOURCES = [os.path.join(CSRC, n) for n in ("element.hip", "device_common.h")]
 MFMA_FILE = os.path.join(ROOT, "profiles", "mfma_busy_energy_jet_fp64_hex8_64cube.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "sq_counters_assembly_kernels_hex8_64cube.txt")
 
 
 def log(msg):
@@ -289,6 +290,28 @@ def profile_record(path, sources, key="jet_source_sha256"):
     return rec
 
 
+def issue_record(kernel):
+    """The instruction-issue row of `kernel` from the committed counter summary,
+    if it was taken on the kernel's current sources; else None."""
+    try:
+        with open(SQ_FILE) as f:
+            rows = json.loads([ln for ln in f if ln.startswith("[")][-1])
+    except (OSError, ValueError, IndexError):
+        return None
+    for r in rows:
+        if r.get("kernel") != kernel:
+            continue
+        h = hashlib.sha256()
+        try:
+            for n in r["hashed_sources"]:
+                with open(os.path.join(CSRC, n), "rb") as f:
+                    h.update(f.read())
+        except (OSError, KeyError):
+            return None
+        return r if r.get("source_sha256") == h.hexdigest() else None
+    return None
+
+
 def jet_traffic():
     """HBM bytes per jet launch from the committed counter summary, or None."""
     rec = profile_record(TRAFFIC_FILE, JET_SOURCES)
@@ -378,14 +401,17 @@ def main():
                     flops_per_qp=jet_flops_per_qp(H, L), qp_per_launch=nq, ms_per_launch=round(jet_ms, 4),
                     issued_flops_per_qp=jet_issued_flops_per_qp(H, L),
                     issued_frac=round(issued_tf / PEAK_FP64_TFLOPS, 4),
-                    mfma_busy_frac=None if mfma is None else mfma.get("mfma_busy_frac"))
+                    mfma_busy_frac=None if mfma is None else mfma.get("mfma_busy_frac"),
+                    valu_issue_frac=(issue_record("jet_f64_kernel<64,3,true>") or {}).get("valu_issue_frac"))
     eb = element_alg_bytes(case, ctx.nnz)
     erec = profile_record(ELEM_TRAFFIC_FILE, ELEM_SOURCES, key="source_sha256")
     element_roofline = dict(bound="hbm", achieved=round(eb / (elem_ms * 1e-3) / 1e9, 1), peak=PEAK_HBM_GBS,
                             unit="GB/s", frac=round(eb / (elem_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                             traffic=None if erec is None else erec.get("bytes_per_assembly"),
                             kernel="element_kernel (all colours of one assembly)", algorithmic_bytes=eb,
-                            ms_per_assembly=round(elem_ms, 4))
+                            ms_per_assembly=round(elem_ms, 4),
+                            valu_issue_frac=(issue_record("element_kernel<3,true> (per colour)") or {}).get(
+                                "valu_issue_frac"))
     log(f"{ms_step:.3f} ms/step; phases ms: inputs {in_ms:.3f} jets {jet_ms:.3f} history {hist_ms:.3f} "
         f"elements {elem_ms:.3f} fills {fill_ms:.3f}")
 
