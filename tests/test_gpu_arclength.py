@@ -24,14 +24,15 @@ from gpu_common import rel_err, sync
 pytestmark = pytest.mark.gpu
 
 
-def _oracle_path(case, bd, bu, ds, n_max, lam_end, **kw):
+def _oracle_path(case, bd, bu, ds, n_max, lam_end, psi=1.0, **kw):
     m = fem.Model(case)
     rd = W.reaction_dofs(case)
     d = fem.dof_vector(case.u, case.phi)
     kap = case.kappa.copy()
     lam, prev, ref = 0.0, None, []
     while len(ref) < n_max and lam < lam_end:
-        d, lam, kt, inc, hist, ok = solve.arclength_step(m, case.mesh, d, lam, kap, bd, bu, ds, prev=prev, **kw)
+        d, lam, kt, inc, hist, ok = solve.arclength_step(m, case.mesh, d, lam, kap, bd, bu, ds, psi=psi, prev=prev,
+                                                         **kw)
         assert ok, len(ref)
         R, _, _ = fem.assemble(m, case.mesh, d, kap, tangent=False)
         kap, prev = kt, inc
@@ -39,14 +40,14 @@ def _oracle_path(case, bd, bu, ds, n_max, lam_end, **kw):
     return ref
 
 
-def _gpu_follow(G, case, bd, bu, ds, ref, lam_tol, state_tol, reaction_tol, **solver):
+def _gpu_follow(G, case, bd, bu, ds, ref, lam_tol, state_tol, reaction_tol, psi=1.0, **solver):
     ctx = G.Context.from_case(case)
     rd = W.reaction_dofs(case)
     u, phi, kg = ctx.fields(case.u, case.phi, case.kappa)
     inc = torch.zeros(ctx.ndof + 1, dtype=torch.float64, device=ctx.dev)
     lam, out = 0.0, []
     for n, (lo, do, ko, ro) in enumerate(ref):
-        lam, rep = ctx.arclength_step(u, phi, kg, bd, bu, lam, inc, ds, 1.0, reaction_dofs=rd, **solver)
+        lam, rep = ctx.arclength_step(u, phi, kg, bd, bu, lam, inc, ds, psi, reaction_dofs=rd, **solver)
         sync()
         uo, po = fem.split_dofs(do, case.mesh.dim)
         print(f"  increment {n}: lambda gpu {lam:.12f} oracle {lo:.12f}; reaction gpu {rep['reaction']:.10e} "
@@ -91,3 +92,16 @@ def test_strip_snap_back_matches_oracle():
     # then grows again while the force keeps falling
     assert (dl < 0.0).sum() >= 5 and dl[-1] > 0.0
     assert (np.diff(f[k:]) < 0.0).all()
+
+
+def test_strip_cylindrical_form_matches_oracle():
+    """psi = 0: the arc length counts the free dofs only (cylindrical form);
+    20 increments of the strip's rising branch."""
+    from paper_2604_03411_amd import gedmg as G
+    case = W.strip_case(nx=20)
+    bd, bu = W.arclength_pattern(case)
+    print("[arc-length] necked Q4 strip 20x1, psi 0, ds 0.1, 20 increments", flush=True)
+    atol = 1e-11
+    ref = _oracle_path(case, bd, bu, 0.1, 20, np.inf, psi=0.0, atol=atol)
+    _gpu_follow(G, case, bd, bu, 0.1, ref, 1e-8, 1e-7, 1e-7, psi=0.0, newton_rtol=0.0, newton_atol=atol,
+                krylov_rtol=1e-13, krylov_method="bicgstab")

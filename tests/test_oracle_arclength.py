@@ -14,18 +14,21 @@ unit face.  Every converged arc-length increment must lie on it."""
 import math
 
 import numpy as np
+import pytest
 
 import workloads as W
 from oracle import fem, solve
 
 
-def test_arclength_states_are_displacement_controlled_equilibria():
+@pytest.mark.parametrize("psi", [1.0, 0.0])
+def test_arclength_states_are_displacement_controlled_equilibria(psi):
+    """psi = 0 is the cylindrical form: the arc length counts the free dofs only."""
     case = W.strip_case(nx=20)
     m = fem.Model(case)
     bd, bu = W.arclength_pattern(case)
     d = fem.dof_vector(case.u, case.phi)
     kap = case.kappa.copy()
-    lam, prev, ds, psi = 0.0, None, 0.1, 1.0
+    lam, prev, ds = 0.0, None, 0.1
     for n in range(8):
         d_prev, k_prev, lam_prev = d.copy(), kap.copy(), lam
         d, lam, kt, inc, hist, ok = solve.arclength_step(m, case.mesh, d, lam, kap, bd, bu, ds, psi=psi, prev=prev,
