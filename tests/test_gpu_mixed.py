@@ -134,6 +134,37 @@ def test_mixed_newton_converges_to_fp64_solution(precision):
         assert ep <= 1e-6 and ek <= 1e-6
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_mixed_staggered_steps_match_oracle(precision):
+    """The staggered scheme (history held in the global solve) with the
+    low-precision tangent: the converged states and reactions equal the
+    oracle's staggered path; and the closed-form model, whose jet is FP64 in
+    every precision, gives the FP64 path's states."""
+    from paper_2604_03411_amd import gedmg as G
+    from test_gpu_newton import run_gpu_path
+    case = W.make_case(3, n=16)
+    case.n_steps = 8
+    du = W.uniaxial_increment(case)
+    print(f"[mixed staggered] notched plate q4 16x16, 4 steps, {precision} vs oracle", flush=True)
+    got = run_gpu_path(G, case, 4, W.uniaxial_bc, precision=precision, predictor_du=du, scheme="staggered")
+    recs = solve.load_path(case, fem.Model(case), steps=4, rtol=0.0, atol=ATOL, scheme="staggered")
+    for (u1, p1, k1, r1), rec in zip(got, recs):
+        uo, po = fem.split_dofs(rec["d"], 2)
+        eu, ep, ek = rel_err(u1, uo), rel_err(p1, po), rel_err(k1, rec["kappa"])
+        er = abs(r1["reaction"] - rec["reaction"]) / abs(rec["reaction"])
+        print(f"  vs oracle: u {eu:.2e} phi {ep:.2e} kappa {ek:.2e} reaction {er:.2e}", flush=True)
+        assert eu <= 1e-8 and er <= 1e-8 and ep <= 1e-6 and ek <= 1e-6
+    plate = W.uniform_plate_case("coarse", n_steps=40, total_disp=40.0)
+    ref = run_gpu_path(G, plate, 4, W.symmetric_tension_bc, precision="fp64",
+                       predictor_du=W.uniaxial_increment(plate), newton_rscale=0.0)
+    low = run_gpu_path(G, plate, 4, W.symmetric_tension_bc, precision=precision,
+                       predictor_du=W.uniaxial_increment(plate), newton_rscale=0.0)
+    for (u0, p0, k0, r0), (u1, p1, k1, r1) in zip(ref, low):
+        print(f"  closed form, {precision} vs fp64: u {rel_err(u1, u0):.2e} kappa {rel_err(k1, k0):.2e} "
+              f"(max kappa {k0.max():.4g})", flush=True)
+        assert rel_err(u1, u0) <= 1e-9 and rel_err(k1, k0) <= 1e-9
+
+
 @pytest.mark.parametrize("precision", ["fp64", "bf16", "fp16"])
 def test_converged_displacement_heterogeneous_cube_vs_oracle(precision):
     """The converged-displacement error of the 3-D heterogeneous-stretch
