@@ -236,3 +236,25 @@ def test_arclength_rejects_invalid_arguments(G):
     assert rc == E_ARG and lamc.value == 0.25
     assert torch.equal(u, u0)
     ctx.close()
+
+
+def test_failed_newton_step_backtracks_and_restores_fields(G):
+    """A load step that cannot be solved fails cleanly.  The 20^3 heterogeneous
+    cube with every boundary node on its seeded field (random phi against
+    beta_d = 1000 drives the interior into damage at once) makes the Newton
+    iteration diverge: its corrections invert elements, each is halved up to
+    12 times, and the step then returns GEDMG_E_JNONPOS with u, phi and kappa
+    exactly as they were passed in."""
+    case = W.make_case(4, n=20)
+    bd, bv = W.boundary_field_bc(case)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    u0, p0, k0 = u.clone(), phi.clone(), kap.clone()
+    print("[edge] diverging Newton step on the 20^3 heterogeneous cube", flush=True)
+    rep = ctx.newton_step(u, phi, kap, bd, bv, raise_on_error=False, max_newton=40, newton_rtol=1e-10,
+                          newton_atol=1e-9 * np.sqrt(case.mesh.ndof))
+    sync()
+    print(f"  status {rep['status']}, iterations {rep['newton_iters']}, backtracks {rep['backtracks']}", flush=True)
+    assert rep["status"] == E_JNONPOS and rep["backtracks"] == 12
+    assert torch.equal(u, u0) and torch.equal(phi, p0) and torch.equal(kap, k0)
+    ctx.close()
