@@ -150,13 +150,16 @@ def loss_and_gradient(case, records, targets, theta_e=None, theta_y=None, react_
 
 
 def arclength_step(model, mesh, d, lam, kappa_n, bc_dofs, bc_unit, ds, psi=1.0, prev=None, rtol=1e-10,
-                   atol=None, max_iter=25, rscale=1.0):
+                   atol=None, max_iter=25, rscale=1.0, phi_weight=1.0):
     """One increment of arc-length continuation for displacement-controlled
     loading (the paper's arc-length remark in Sec. 3.2 and its use in Sec. 5.1):
     the prescribed dofs carry lam * bc_unit, and the load factor lam is an
     unknown next to the free dofs, tied by the constraint
-    ||Delta d_f||^2 + psi^2 Delta lam^2 = ds^2 (Riks: the corrector iterates in
-    the plane normal to the predictor).
+    ||Delta d_f||_W^2 + psi^2 Delta lam^2 = ds^2 (Riks: the corrector iterates in
+    the plane normal to the predictor).  ||.||_W weights the nonlocal damage
+    dofs by phi_weight (1: the plain norm of all free dofs; 0: the displacement
+    dofs only, for problems where phi, an energy-like field, would dominate
+    the length of an increment).
 
     Predictor: the previous increment `prev` = (Delta d_f, Delta lam) scaled to
     length ds (secant); for the first increment (prev None) the tangent
@@ -176,6 +179,12 @@ def arclength_step(model, mesh, d, lam, kappa_n, bc_dofs, bc_unit, ds, psi=1.0, 
     atol = default_atol(mesh) if atol is None else atol
     free = np.ones(mesh.ndof, bool)
     free[bc_dofs] = False
+    nd = mesh.dim + 1
+    wt = np.where(np.arange(mesh.ndof) % nd == nd - 1, phi_weight * phi_weight, 1.0)[free]
+
+    def wdot(a, b):
+        return float(np.sum(wt * a * b))
+
     uhat = np.zeros(mesh.ndof)
     uhat[bc_dofs] = bc_unit
     d = np.array(d, dtype=np.float64, copy=True)
@@ -183,14 +192,14 @@ def arclength_step(model, mesh, d, lam, kappa_n, bc_dofs, bc_unit, ds, psi=1.0, 
     d0f = d[free].copy()
     lam0 = lam
     if prev is not None:
-        scale = ds / np.sqrt(float(prev[0] @ prev[0]) + psi * psi * prev[1] ** 2)
+        scale = ds / np.sqrt(wdot(prev[0], prev[0]) + psi * psi * prev[1] ** 2)
         dd_p = scale * np.asarray(prev[0])
         dlam_p = scale * prev[1]
     else:
         R, K, _ = fem.assemble(model, mesh, d, kappa_n, update_history=False)
         Kff = K[free][:, free].tocsc()
         t = spla.spsolve(Kff, -(K @ uhat)[free])
-        dlam_p = ds / np.sqrt(t @ t + psi * psi)
+        dlam_p = ds / np.sqrt(wdot(t, t) + psi * psi)
         dd_p = dlam_p * t
     lam = lam0 + dlam_p
     d[free] = d0f + dd_p
@@ -211,7 +220,7 @@ def arclength_step(model, mesh, d, lam, kappa_n, bc_dofs, bc_unit, ds, psi=1.0, 
         lu = spla.splu(Kff)
         a = lu.solve(-Rf)
         b = lu.solve(-(K @ uhat)[free])
-        dl = -float(dd_p @ a) / float(dd_p @ b + psi * psi * dlam_p)
+        dl = -wdot(dd_p, a) / (wdot(dd_p, b) + psi * psi * dlam_p)
         d[free] += a + dl * b
         lam += dl
         d[bc_dofs] = lam * np.asarray(bc_unit)

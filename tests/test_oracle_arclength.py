@@ -20,9 +20,10 @@ import workloads as W
 from oracle import fem, solve
 
 
-@pytest.mark.parametrize("psi", [1.0, 0.0])
-def test_arclength_states_are_displacement_controlled_equilibria(psi):
-    """psi = 0 is the cylindrical form: the arc length counts the free dofs only."""
+@pytest.mark.parametrize("psi,wphi", [(1.0, 1.0), (0.0, 1.0), (1.0, 0.0)])
+def test_arclength_states_are_displacement_controlled_equilibria(psi, wphi):
+    """psi = 0 is the cylindrical form: the arc length counts the free dofs
+    only; wphi = 0 leaves the nonlocal damage dofs out of it."""
     case = W.strip_case(nx=20)
     m = fem.Model(case)
     bd, bu = W.arclength_pattern(case)
@@ -32,10 +33,13 @@ def test_arclength_states_are_displacement_controlled_equilibria(psi):
     for n in range(8):
         d_prev, k_prev, lam_prev = d.copy(), kap.copy(), lam
         d, lam, kt, inc, hist, ok = solve.arclength_step(m, case.mesh, d, lam, kap, bd, bu, ds, psi=psi, prev=prev,
-                                                         atol=1e-11)
+                                                         atol=1e-11, phi_weight=wphi)
         assert ok
         assert lam > lam_prev  # rising part of the path
-        L2 = float(inc[0] @ inc[0] + psi * psi * inc[1] ** 2)
+        free = np.ones(case.mesh.ndof, bool)
+        free[bd] = False
+        wt = np.where(np.arange(case.mesh.ndof) % 3 == 2, wphi * wphi, 1.0)[free]
+        L2 = float(np.sum(wt * inc[0] * inc[0]) + psi * psi * inc[1] ** 2)
         assert L2 >= ds * ds * (1.0 - 1e-12)
         # displacement control to the same load factor from the same start
         dc, kc, h2, ok2 = solve.newton(m, case.mesh, d_prev, k_prev, bd, lam * bu, rtol=0.0, atol=1e-11)
