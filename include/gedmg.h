@@ -300,7 +300,7 @@ int gedmg_newton_step(gedmg_ctx* ctx, const gedmg_dirichlet* bc, const gedmg_sol
  * arc-length continuation, Sec. 5.1; Sec. 3.2 names the approach): the
  * prescribed dofs carry lambda times their unit values pattern->value, and the
  * load factor lambda is solved for together with the free dofs under
- * ||Delta d_f||^2 + psi^2 Delta lambda^2 = ds^2, so the path is followed
+ * ||Delta d_f||_W^2 + psi^2 Delta lambda^2 = ds^2, so the path is followed
  * through limit points of the load factor (snap-back), where displacement
  * control has no solution nearby.  Riks' scheme: the predictor is the previous
  * increment scaled to length ds (secant); for a first increment (increment all
@@ -314,6 +314,11 @@ int gedmg_newton_step(gedmg_ctx* ctx, const gedmg_dirichlet* bc, const gedmg_sol
  * scheme and refine_* are ignored).
  *   pattern     Dirichlet set: device dof indices and their unit values uhat
  *   ds, psi     arc length (> 0) and load-factor scale (>= 0; 0: cylindrical)
+ *   phi_weight  weight (>= 0, finite) of the nonlocal damage dofs in ||.||_W, the
+ *               displacement dofs having weight 1: 1 gives the plain norm of
+ *               all free dofs; phi is an energy-like field, and where its
+ *               increments outgrow the displacements' (a notched plate), 0
+ *               measures the arc length in displacements only
  *   lambda      host, in: the load factor of the state passed in; out: the
  *               converged one
  *   increment   device [ndof + 1], in: the previous increment (free dofs in the
@@ -325,8 +330,8 @@ int gedmg_newton_step(gedmg_ctx* ctx, const gedmg_dirichlet* bc, const gedmg_sol
  * call for a context.  Errors: those of gedmg_newton_step, GEDMG_E_LINSOLVE
  * when the constraint cannot be solved (Dd . b + psi^2 Dlambda = 0). */
 int gedmg_arclength_step(gedmg_ctx* ctx, const gedmg_dirichlet* pattern, const gedmg_solver_opts* opts,
-                         double ds, double psi, double* lambda, double* increment, double* u, double* phi,
-                         double* kappa, const int32_t* reaction_dofs, int32_t n_reaction,
+                         double ds, double psi, double phi_weight, double* lambda, double* increment, double* u,
+                         double* phi, double* kappa, const int32_t* reaction_dofs, int32_t n_reaction,
                          gedmg_newton_report* report);
 
 /* Gradient of the load-path loss L = sum_n (r_n - t_n)^2, r_n the reaction of

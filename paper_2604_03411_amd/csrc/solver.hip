@@ -243,6 +243,17 @@ __global__ void dot2_kernel(const double* a, const double* b, const double* c, c
   if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = t2;
 }
 
+// Partials of a . b with the nonlocal damage dofs (every nd-th, last of a
+// node) weighted by w2 and the others by 1: the arc-length norm.
+__global__ void wdot_kernel(const double* a, const double* b, long n, int nd, double w2, double* part) {
+  __shared__ double sh[8];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    s += ((i % nd) == nd - 1 ? w2 : 1.0) * a[i] * b[i];
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 // One-block reduction of kRedBlocks partials into scal[slot] (fixed order).
 __global__ void reduce_kernel(const double* part, double* scal, int slot, int slot2) {
   __shared__ double sh[8];
@@ -587,16 +598,15 @@ int dot2(gedmg_ctx* c, Work& w, const double* a, const double* b, const double* 
 
 int read_scalars(gedmg_ctx* c, Work& w);
 
-// a . b (and c . d when c is given) over all dofs, read back to the host.
-int dots(gedmg_ctx* c, Work& w, const double* a, const double* b, const double* c2, const double* d2, double* ab,
-         double* cd) {
-  hipLaunchKernelGGL(dot2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, a, b, c2, d2, w.ndof, w.part);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_TT, c2 ? S_TS : -1);
+// a .W b for the arc-length norm, read back to the host.
+int wdot(gedmg_ctx* c, Work& w, const double* a, const double* b, double w2, double* out) {
+  hipLaunchKernelGGL(wdot_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, a, b, w.ndof, c->dim + 1, w2,
+                     w.part);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_TT, -1);
   GH(hipGetLastError());
   const int rc = read_scalars(c, w);
   if (rc) return rc;
-  *ab = w.hscal[S_TT];
-  if (cd) *cd = w.hscal[S_TS];
+  *out = w.hscal[S_TT];
   return GEDMG_OK;
 }
 
@@ -996,13 +1006,13 @@ extern "C" int gedmg_newton_step(gedmg_ctx* c, const gedmg_dirichlet* bc, const 
 // tangent, two Krylov solves a = -K_ff^-1 R_f, b = -K_ff^-1 y_f, and
 // dlambda = -(Dd . a) / (Dd . b + psi^2 Dlambda), dd = a + dlambda b.
 extern "C" int gedmg_arclength_step(gedmg_ctx* c, const gedmg_dirichlet* pattern, const gedmg_solver_opts* opts_in,
-                                    double ds, double psi, double* lambda, double* increment, double* u,
-                                    double* phi, double* kappa, const int32_t* reaction_dofs, int32_t n_reaction,
-                                    gedmg_newton_report* rep) {
+                                    double ds, double psi, double phi_weight, double* lambda, double* increment,
+                                    double* u, double* phi, double* kappa, const int32_t* reaction_dofs,
+                                    int32_t n_reaction, gedmg_newton_report* rep) {
   if (!c) return GEDMG_E_ARG;
   if (!pattern || pattern->n <= 0 || !pattern->dof || !pattern->value || !lambda || !increment || !u || !phi ||
       !kappa || (n_reaction > 0 && !reaction_dofs) || n_reaction < 0 || !(ds > 0.0) || !(psi >= 0.0) ||
-      !std::isfinite(*lambda)) {
+      !(phi_weight >= 0.0) || !std::isfinite(phi_weight) || !std::isfinite(*lambda)) {
     c->err = "null or inconsistent arc-length argument";
     return GEDMG_E_ARG;
   }
@@ -1107,8 +1117,9 @@ extern "C" int gedmg_arclength_step(gedmg_ctx* c, const gedmg_dirichlet* pattern
   // rounding; neither predictor depends on that choice.
   if ((rc = set_prescribed(lam0))) return rollback(rc);
   double res2 = 0.0;
+  const double w2 = phi_weight * phi_weight;
   double pp = 0.0;
-  if ((rc = dots(c, w, increment, increment, nullptr, nullptr, &pp, nullptr))) return rollback(rc);
+  if ((rc = wdot(c, w, increment, increment, w2, &pp))) return rollback(rc);
   const double prev_len2 = pp + psi * psi * prev_dlam * prev_dlam;
   double dlam_p = 0.0;
   if (prev_len2 > 0.0 && std::isfinite(prev_len2)) {
@@ -1131,7 +1142,7 @@ extern "C" int gedmg_arclength_step(gedmg_ctx* c, const gedmg_dirichlet* pattern
     GH(hipGetLastError());
     if ((rc = solve_into(w.al_dp, o.krylov_rtol))) return rollback(rc);
     double tt = 0.0;
-    if ((rc = dots(c, w, w.al_dp, w.al_dp, nullptr, nullptr, &tt, nullptr))) return rollback(rc);
+    if ((rc = wdot(c, w, w.al_dp, w.al_dp, w2, &tt))) return rollback(rc);
     dlam_p = ds / std::sqrt(tt + psi * psi);
     hipLaunchKernelGGL(axpy_scalar_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, w.al_dp, dlam_p - 1.0,
                        w.al_dp, n);  // al_dp = dlam_p * t
@@ -1186,7 +1197,8 @@ extern "C" int gedmg_arclength_step(gedmg_ctx* c, const gedmg_dirichlet* pattern
     r.krylov_iters_total += its;
     if (rc) return rollback(rc);
     double da = 0.0, db = 0.0;
-    if ((rc = dots(c, w, w.al_dp, w.al_a, w.al_dp, w.x, &da, &db))) return rollback(rc);
+    if ((rc = wdot(c, w, w.al_dp, w.al_a, w2, &da)) || (rc = wdot(c, w, w.al_dp, w.x, w2, &db)))
+      return rollback(rc);
     const double den = db + psi * psi * dlam_p;
     if (!(std::fabs(den) > 0.0)) { c->err = "arc-length corrector breakdown"; return rollback(GEDMG_E_LINSOLVE); }
     const double dl = -da / den;

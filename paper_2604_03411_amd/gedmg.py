@@ -132,7 +132,7 @@ def lib():
             L.gedmg_newton_step.argtypes = [vp, C.POINTER(Dirichlet), C.POINTER(SolverOpts), C.c_int,
                                             vp, vp, vp, vp, vp, i32, C.POINTER(NewtonReport)]
         if hasattr(L, "gedmg_arclength_step"):
-            L.gedmg_arclength_step.argtypes = [vp, C.POINTER(Dirichlet), C.POINTER(SolverOpts), dp, dp,
+            L.gedmg_arclength_step.argtypes = [vp, C.POINTER(Dirichlet), C.POINTER(SolverOpts), dp, dp, dp,
                                                C.POINTER(dp), vp, vp, vp, vp, vp, i32, C.POINTER(NewtonReport)]
         if hasattr(L, "gedmg_adjoint"):
             L.gedmg_adjoint.argtypes = [vp, i32, C.POINTER(Dirichlet), vp, vp, i32, vp, i32,
@@ -374,10 +374,11 @@ class Context:
         return out
 
     def arclength_step(self, u, phi, kappa, pattern_dofs, pattern_unit, lam, increment, ds, psi=1.0,
-                       reaction_dofs=None, raise_on_error=True, **solver):
+                       reaction_dofs=None, raise_on_error=True, phi_weight=1.0, **solver):
         """One arc-length increment in place on (u, phi, kappa) and the device
-        array increment [ndof + 1] (gedmg_arclength_step).  Returns (lambda,
-        report dict)."""
+        array increment [ndof + 1] (gedmg_arclength_step; phi_weight weights
+        the nonlocal damage dofs in the arc length).  Returns (lambda, report
+        dict)."""
         self._check_fields(u, phi, kappa)
         _check_array(increment, self.ndof + 1, self.dev, "increment")
         dofs = _dof_index_array(pattern_dofs, self.ndof, self.dev, "pattern_dofs")
@@ -393,7 +394,8 @@ class Context:
             nr = int(rd.numel())
         lamc = C.c_double(float(lam))
         rep = NewtonReport()
-        rc = lib().gedmg_arclength_step(self._h, C.byref(pat), C.byref(opts), float(ds), float(psi), C.byref(lamc),
+        rc = lib().gedmg_arclength_step(self._h, C.byref(pat), C.byref(opts), float(ds), float(psi),
+                                        float(phi_weight), C.byref(lamc),
                                         _dptr(increment), _dptr(u), _dptr(phi), _dptr(kappa), _dptr(rd), nr,
                                         C.byref(rep))
         out = dict(status=rc, newton_iters=rep.newton_iters, krylov_iters=rep.krylov_iters_total,

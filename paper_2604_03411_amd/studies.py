@@ -17,6 +17,9 @@ scalars (reaction, the largest history value) between increments.
   the gradient-enhanced model under the monolithic or the staggered scheme, on
   a coarse, a refined or a non-uniform mesh.  Stops when the largest damage
   reaches d_stop (the paper's 0.995) or the solver fails.
+* notched_arclength: the notched plate of the mixed-precision workload
+  (Q4 256 x 256, network model) by arc-length continuation past its force
+  maximum into softening.
 * train_icnn: fitting both networks to a reaction-force curve of a cyclic
   (load / unload / reload) homogeneous test through the load-path adjoint,
   the use Sec. 4.2.1 describes for stress-stretch data (here synthetic: a
@@ -26,6 +29,7 @@ Usage:
     python -m paper_2604_03411_amd.studies single-element
     python -m paper_2604_03411_amd.studies plate [--steps 1000] [--total 80]
     python -m paper_2604_03411_amd.studies train [--steps 60] [--lr 2e-3]
+    python -m paper_2604_03411_amd.studies notched-arclength [--steps 200]
 (one JSON line per run on stdout).
 """
 from __future__ import annotations
@@ -132,6 +136,40 @@ def uniform_plate(mesh_kind="coarse", model="nonlocal", scheme="monolithic", n_s
                 steps=rows)
 
 
+def notched_arclength(n=256, ds=1.0, lam_end=0.35, max_increments=200, drop=0.5):
+    """The notched plate (Q4 n x n, network model) by arc-length continuation
+    past its force maximum, the arc length measured in displacements only
+    (phi_weight = 0).  Stops at lam_end, after max_increments, or when the
+    force has fallen below `drop` times its maximum."""
+    case = W.make_case(3, n=n)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    bd, bu = W.arclength_pattern(case)
+    rd = W.reaction_dofs(case)
+    inc = torch.zeros(ctx.ndof + 1, dtype=torch.float64, device=ctx.dev)
+    lam, rows, status, fmax = 0.0, [], "reached the end load", 0.0
+    t0 = time.perf_counter()
+    for i in range(max_increments):
+        lam, rep = ctx.arclength_step(u, phi, kap, bd, bu, lam, inc, ds, 1.0, reaction_dofs=rd, phi_weight=0.0,
+                                      raise_on_error=False)
+        if rep["status"] != 0:
+            status = f"increment {i} failed ({G.ERRORS.get(rep['status'], rep['status'])})"
+            break
+        f = rep["reaction"]
+        fmax = max(fmax, f)
+        rows.append(dict(lam=lam, reaction=f, kappa_max=float(kap.max()), newton_iters=rep["newton_iters"],
+                         krylov_iters=rep["krylov_iters"]))
+        if lam >= lam_end:
+            break
+        if f < drop * fmax:
+            status = f"force below {drop} of its maximum"
+            break
+    torch.cuda.synchronize()
+    ctx.close()
+    return dict(study="notched_arclength", n=n, ds=ds, elements=case.mesh.n_elems, dofs=case.mesh.ndof,
+                status=status, wall_s=time.perf_counter() - t0, steps=rows)
+
+
 def training_path(case, ctx, targets=None, checkpoint_every=6):
     """The cyclic load path of a training case as a gedmg LoadPath.  Without
     targets, they are computed by a forward run with the teacher's parameters."""
@@ -175,7 +213,7 @@ def train_icnn(case=None, iters=60, lr=2e-3, log=None):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("study", choices=["single-element", "plate", "train"])
+    ap.add_argument("study", choices=["single-element", "plate", "train", "notched-arclength"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--total", type=float, default=None)
     ap.add_argument("--every", type=int, default=1, help="keep every k-th step in the output")
@@ -187,6 +225,14 @@ def main():
     if args.study == "train":
         r = train_icnn(iters=args.steps or 60, lr=args.lr or 2e-3,
                        log=lambda m: print(f"[train] {m}", file=sys.stderr, flush=True))
+        print(json.dumps(r), flush=True)
+        return
+    if args.study == "notched-arclength":
+        r = notched_arclength(max_increments=args.steps or 200)
+        last = r["steps"][-1] if r["steps"] else {}
+        print(f"[notched] {r['status']}; {len(r['steps'])} increments, lambda {last.get('lam')}, "
+              f"{r['wall_s']:.1f} s", file=sys.stderr, flush=True)
+        r["steps"] = r["steps"][::args.every]
         print(json.dumps(r), flush=True)
         return
     if args.study == "single-element":

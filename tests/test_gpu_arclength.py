@@ -5,6 +5,9 @@ oracle's Riks increments.
   kappa_d = 1): the path rises to the peak force and follows the softening
   branch until the force is below 1e-3 of the peak, to 0.5 mm.  The oracle's
   increments are pinned to the closed-form uniaxial path on the CPU.
+* The notched plate (Q4 16x16, the network model of the notched-plate
+  workload), with the arc length measured in displacements only
+  (phi_weight = 0): 26 increments through the force maximum into softening.
 * The necked Q4 strip of 20 elements (gradient-enhanced closed-form model,
   eta_d = 2): 60 increments.  Past the force maximum the damage localises in
   the neck while the rest of the strip unloads, and the end displacement
@@ -24,7 +27,7 @@ from gpu_common import rel_err, sync
 pytestmark = pytest.mark.gpu
 
 
-def _oracle_path(case, bd, bu, ds, n_max, lam_end, psi=1.0, **kw):
+def _oracle_path(case, bd, bu, ds, n_max, lam_end, psi=1.0, phi_weight=1.0, **kw):
     m = fem.Model(case)
     rd = W.reaction_dofs(case)
     d = fem.dof_vector(case.u, case.phi)
@@ -32,7 +35,7 @@ def _oracle_path(case, bd, bu, ds, n_max, lam_end, psi=1.0, **kw):
     lam, prev, ref = 0.0, None, []
     while len(ref) < n_max and lam < lam_end:
         d, lam, kt, inc, hist, ok = solve.arclength_step(m, case.mesh, d, lam, kap, bd, bu, ds, psi=psi, prev=prev,
-                                                         **kw)
+                                                         phi_weight=phi_weight, **kw)
         assert ok, len(ref)
         R, _, _ = fem.assemble(m, case.mesh, d, kap, tangent=False)
         kap, prev = kt, inc
@@ -40,14 +43,16 @@ def _oracle_path(case, bd, bu, ds, n_max, lam_end, psi=1.0, **kw):
     return ref
 
 
-def _gpu_follow(G, case, bd, bu, ds, ref, lam_tol, state_tol, reaction_tol, psi=1.0, **solver):
+def _gpu_follow(G, case, bd, bu, ds, ref, lam_tol, state_tol, reaction_tol, psi=1.0, phi_weight=1.0,
+                damage_tol=None, **solver):
     ctx = G.Context.from_case(case)
     rd = W.reaction_dofs(case)
     u, phi, kg = ctx.fields(case.u, case.phi, case.kappa)
     inc = torch.zeros(ctx.ndof + 1, dtype=torch.float64, device=ctx.dev)
     lam, out = 0.0, []
     for n, (lo, do, ko, ro) in enumerate(ref):
-        lam, rep = ctx.arclength_step(u, phi, kg, bd, bu, lam, inc, ds, psi, reaction_dofs=rd, **solver)
+        lam, rep = ctx.arclength_step(u, phi, kg, bd, bu, lam, inc, ds, psi, reaction_dofs=rd, phi_weight=phi_weight,
+                                      **solver)
         sync()
         uo, po = fem.split_dofs(do, case.mesh.dim)
         print(f"  increment {n}: lambda gpu {lam:.12f} oracle {lo:.12f}; reaction gpu {rep['reaction']:.10e} "
@@ -55,7 +60,7 @@ def _gpu_follow(G, case, bd, bu, ds, ref, lam_tol, state_tol, reaction_tol, psi=
         assert abs(lam - lo) <= lam_tol * abs(lo)
         assert abs(rep["reaction"] - ro) <= reaction_tol * abs(ro)
         assert rel_err(u.cpu().numpy(), uo) <= state_tol
-        assert rel_err(kg.cpu().numpy(), ko) <= state_tol
+        assert rel_err(kg.cpu().numpy(), ko) <= (damage_tol or state_tol)
         out.append(rep["reaction"])
     ctx.close()
     return np.array(out)
@@ -105,3 +110,23 @@ def test_strip_cylindrical_form_matches_oracle():
     ref = _oracle_path(case, bd, bu, 0.1, 20, np.inf, psi=0.0, atol=atol)
     _gpu_follow(G, case, bd, bu, 0.1, ref, 1e-8, 1e-7, 1e-7, psi=0.0, newton_rtol=0.0, newton_atol=atol,
                 krylov_rtol=1e-13, krylov_method="bicgstab")
+
+
+def test_notched_plate_past_the_peak_matches_oracle():
+    """The notched plate (network model) followed by arc-length continuation
+    with the arc length in displacements only: phi, an energy-like field,
+    would otherwise take up the whole arc length of every increment."""
+    from paper_2604_03411_amd import gedmg as G
+    case = W.make_case(3, n=16)
+    bd, bu = W.arclength_pattern(case)
+    print("[arc-length] notched plate q4 16x16, phi_weight 0, ds 0.1, 26 increments", flush=True)
+    atol = 1e-11
+    ref = _oracle_path(case, bd, bu, 0.1, 26, np.inf, phi_weight=0.0, atol=atol)
+    # kappa carries the soft uniform-damage mode: at |R_f| <= 1e-11 both sides
+    # leave it determined to about 1e-6 (measured 1.1e-6 at the first
+    # increment), and the reaction through f_d(kappa) to a few 1e-7 (measured
+    # 2e-7); the load factor is determined to 1e-12
+    f = _gpu_follow(G, case, bd, bu, 0.1, ref, 1e-8, 1e-8, 1e-6, phi_weight=0.0, damage_tol=1e-5, newton_rtol=0.0,
+                    newton_atol=atol, krylov_rtol=1e-13, krylov_method="bicgstab")
+    k = int(f.argmax())
+    assert 0 < k < len(f) - 1 and f[-1] < 0.85 * f[k]  # past the peak, on the softening branch

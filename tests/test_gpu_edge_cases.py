@@ -207,9 +207,9 @@ def test_history_at_kappa_d(G):
 
 def test_arclength_rejects_invalid_arguments(G):
     """gedmg_arclength_step's own checks (a C caller has no binding in front):
-    non-positive arc length, negative load-factor scale, a non-finite load
-    factor, pattern dofs out of range; each GEDMG_E_ARG with u, phi and lambda
-    untouched."""
+    non-positive arc length, negative load-factor scale or damage weight, a
+    non-finite load factor, pattern dofs out of range; each GEDMG_E_ARG with
+    u, phi and lambda untouched."""
     case = W.strip_case(nx=4)
     ctx = G.Context.from_case(case)
     u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
@@ -218,8 +218,9 @@ def test_arclength_rejects_invalid_arguments(G):
     bd, bu = W.arclength_pattern(case)
     print("[edge] arc-length argument checks", flush=True)
     for kw in (dict(ds=0.0, psi=1.0, lam=0.0), dict(ds=-0.1, psi=1.0, lam=0.0), dict(ds=0.1, psi=-1.0, lam=0.0),
-               dict(ds=0.1, psi=1.0, lam=float("nan"))):
-        lam, rep = ctx.arclength_step(u, phi, kap, bd, bu, kw["lam"], inc, kw["ds"], kw["psi"], raise_on_error=False)
+               dict(ds=0.1, psi=1.0, lam=float("nan")), dict(ds=0.1, psi=1.0, lam=0.0, wphi=-1.0)):
+        lam, rep = ctx.arclength_step(u, phi, kap, bd, bu, kw["lam"], inc, kw["ds"], kw["psi"], raise_on_error=False,
+                                      phi_weight=kw.get("wphi", 1.0))
         sync()
         assert rep["status"] == E_ARG, kw
     import ctypes as C
@@ -229,7 +230,7 @@ def test_arclength_rejects_invalid_arguments(G):
     lamc = C.c_double(0.25)
     rep = G.NewtonReport()
     opts = G.solver_opts()
-    rc = G.lib().gedmg_arclength_step(ctx._h, C.byref(pat), C.byref(opts), 0.1, 1.0, C.byref(lamc),
+    rc = G.lib().gedmg_arclength_step(ctx._h, C.byref(pat), C.byref(opts), 0.1, 1.0, 1.0, C.byref(lamc),
                                       C.c_void_p(inc.data_ptr()), C.c_void_p(u.data_ptr()),
                                       C.c_void_p(phi.data_ptr()), C.c_void_p(kap.data_ptr()), None, 0, C.byref(rep))
     sync()
