@@ -21,6 +21,11 @@
 namespace gedmg {
 
 constexpr int kRedBlocks = 512;  // blocks of every reduction kernel
+// Krylov solves multiply an ELL copy of the masked matrix: kEllSlots slots per
+// lane, 1 to kEllMaxLanes lanes per row, enough for the longest row.
+constexpr int kEllSlots = 27;
+constexpr int kEllMaxLanes = 64;
+constexpr int kEllMaxBlocks = 2048;  // grid cap of the ELL products (partials)
 constexpr int kMaxBacktracks = 12;  // halvings of one Newton correction
 constexpr int kThreads = 256;
 
@@ -254,11 +259,12 @@ __global__ void wdot_kernel(const double* a, const double* b, long n, int nd, do
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// One-block reduction of kRedBlocks partials into scal[slot] (fixed order).
-__global__ void reduce_kernel(const double* part, double* scal, int slot, int slot2) {
+// One-block reduction of np partials into scal[slot] (fixed order); a second
+// array of np partials at part + kRedBlocks goes to scal[slot2].
+__global__ void reduce_kernel(const double* part, double* scal, int slot, int slot2, int np) {
   __shared__ double sh[8];
   double s = 0.0, s2 = 0.0;
-  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) {
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
     s += part[i];
     if (slot2 >= 0) s2 += part[kRedBlocks + i];
   }
@@ -290,16 +296,18 @@ __global__ void coarse_energy_kernel(const double* K, const int32_t* rowptr, con
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// partial sums of r.D^-1.r, r.r and chi.r
-__global__ void cg_init_kernel(const double* r, const double* dinv, const uint8_t* mask, int nd, long n,
-                               double* part) {
+// partial sums of r.D^-1.r, r.r and chi.r; zd = D^-1 r
+__global__ void cg_init_kernel(const double* r, const double* dinv, const uint8_t* chif, long n, double* part,
+                               double* zd) {
   __shared__ double sh[8];
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const double ri = r[i];
-    s1 += ri * dinv[i] * ri;
+    const double zi = dinv[i] * ri;
+    zd[i] = zi;
+    s1 += ri * zi;
     s2 += ri * ri;
-    if (chi(i, nd, mask)) s3 += ri;
+    if (chif[i]) s3 += ri;
   }
   double t = block_sum(s1, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -309,23 +317,24 @@ __global__ void cg_init_kernel(const double* r, const double* dinv, const uint8_
   if (threadIdx.x == 0) part[2 * kRedBlocks + blockIdx.x] = t;
 }
 
-// Every block sums the SpMV kernel's partials of p.Ap itself (same order in
-// every block, so all blocks get the same alpha); block 0 publishes it.
-__device__ __forceinline__ double block_total(const double* part, double* sh, double* bc) {
+// Every block sums the np partials of p.Ap of the sparse product itself (same
+// order in every block, so all blocks get the same alpha); block 0 publishes it.
+__device__ __forceinline__ double block_total(const double* part, int np, double* sh, double* bc) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) s += part[i];
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
   const double t = block_sum(s, sh);
   if (threadIdx.x == 0) *bc = t;
   __syncthreads();
   return *bc;
 }
 
+// x += alpha p, r -= alpha q, zd = D^-1 r; partials of r.D^-1.r, r.r and chi.r
 __global__ void cg_update_kernel(double* x, double* r, const double* p, const double* Ap, const double* dinv,
-                                 const uint8_t* mask, int nd, double* scal, int ra, long n,
-                                 const double* part_pap, double* part) {
+                                 const uint8_t* chif, double* scal, int ra, long n, const double* part_pap,
+                                 int npap, double* part, double* zd) {
   __shared__ double sh[8];
   __shared__ double bc;
-  const double pap = block_total(part_pap, sh, &bc);
+  const double pap = block_total(part_pap, npap, sh, &bc);
   const double alpha = (pap > 0.0) ? scal[ra] / pap : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     scal[S_PAP] = pap;
@@ -336,9 +345,11 @@ __global__ void cg_update_kernel(double* x, double* r, const double* p, const do
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * Ap[i];
     r[i] = ri;
-    s1 += ri * dinv[i] * ri;
+    const double zi = dinv[i] * ri;
+    zd[i] = zi;
+    s1 += ri * zi;
     s2 += ri * ri;
-    if (chi(i, nd, mask)) s3 += ri;
+    if (chif[i]) s3 += ri;
   }
   double t = block_sum(s1, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -348,17 +359,120 @@ __global__ void cg_update_kernel(double* x, double* r, const double* p, const do
   if (threadIdx.x == 0) part[2 * kRedBlocks + blockIdx.x] = t;
 }
 
-// p = z + beta p, z = D^-1 r + cc chi, beta = (r.z)_new / (r.z); first = 1
-// starts the recurrence (beta = 0).  Every block sums the three partial
-// arrays of the update kernel itself (same order everywhere): cc = (chi.r)/E,
-// (r.z)_new = r.D^-1.r + cc (chi.r); block 0 publishes them in scal[S_CC],
-// scal[rb] and r.r in scal[S_RR].
-__global__ void cg_p_kernel(double* p, const double* r, const double* dinv, const uint8_t* mask, int nd,
-                            const double* part, double* scal, int ra, int rb, int first, long n) {
+// ---- ELL copy of the masked matrix for the Krylov iterations.  Slot s of a
+// row (its s-th CSR entry, or a zero on the row's own column past its length)
+// is stored at ((s / L) * nrows + row) * L + s % L: the L lanes of a row and
+// consecutive rows read consecutive words, and no row length is loaded.
+__global__ void ell_cols_kernel(const int32_t* rowptr, const int32_t* col, long nrows, int L, int32_t* ecol) {
+  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nrows) return;
+  const int j0 = rowptr[row], len = rowptr[row + 1] - j0;
+  for (int s = 0; s < L * kEllSlots; ++s)
+    ecol[((long)(s / L) * nrows + row) * L + s % L] = s < len ? col[j0 + s] : (int32_t)row;
+}
+
+// ELL values of K, and the chi flags of this solve's mask
+__global__ void ell_pack_kernel(const double* K, const int32_t* rowptr, const uint8_t* mask, int nd, long nrows,
+                                int L, double* eval, uint8_t* chif) {
+  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nrows) return;
+  const int j0 = rowptr[row], len = rowptr[row + 1] - j0;
+  for (int s = 0; s < L * kEllSlots; ++s)
+    eval[((long)(s / L) * nrows + row) * L + s % L] = s < len ? K[j0 + s] : 0.0;
+  chif[row] = chi(row, nd, mask);
+}
+
+// y = K x from the ELL copy (L lanes per row) and partials of w . y
+template <int L>
+__global__ __launch_bounds__(256) void ell_spmv_kernel(const double* eval, const int32_t* ecol, const double* x,
+                                                       double* y, const double* w, long nrows, double* part) {
+  __shared__ double sh[8];
+  const int lane = threadIdx.x % L;
+  const long groups = (long)gridDim.x * (blockDim.x / L);
+  double acc = 0.0;
+  for (long row = (long)blockIdx.x * (blockDim.x / L) + threadIdx.x / L; row < nrows; row += groups) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kEllSlots; ++k) {
+      const long idx = ((long)k * nrows + row) * L + lane;
+      s += eval[idx] * x[ecol[idx]];
+    }
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, L);
+    if (lane == 0) {
+      y[row] = s;
+      if (w) acc += w[row] * s;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// The slots of one row of the ELL copy with every operand of its product that
+// does not depend on this iteration's scalars: column values, and D^-1 r, the
+// previous direction and the chi flag at each column and at the row itself.
+struct EllRow {
+  double val[kEllSlots], zd[kEllSlots], po[kEllSlots];
+  uint8_t cf[kEllSlots];
+  double zd_own, po_own;
+  uint8_t cf_own;
+};
+
+template <int L>
+__device__ __forceinline__ void ell_row_load(EllRow& e, long row, int lane, long nrows, const double* eval,
+                                             const int32_t* ecol, const double* zd, const uint8_t* chif,
+                                             const double* p_old) {
+  if (row >= nrows) return;
+  int col[kEllSlots];
+#pragma unroll
+  for (int k = 0; k < kEllSlots; ++k) {
+    const long idx = ((long)k * nrows + row) * L + lane;
+    col[k] = ecol[idx];
+    e.val[k] = eval[idx];
+  }
+#pragma unroll
+  for (int k = 0; k < kEllSlots; ++k) {
+    e.zd[k] = zd[col[k]];
+    e.po[k] = p_old[col[k]];
+    e.cf[k] = chif[col[k]];
+  }
+  e.zd_own = zd[row];
+  e.po_own = p_old[row];
+  e.cf_own = chif[row];
+}
+
+// Entry of the new search direction p = z + beta p_old, z = D^-1 r + cc chi,
+// from the loaded operands.  The first direction is z: beta = 0 and p_old is
+// zeroed at the start of the solve.
+__device__ __forceinline__ double cg_dir(double zd, double po, uint8_t cf, double cc, double beta) {
+  return fma(beta, po, zd + (cf ? cc : 0.0));
+}
+
+// The new search direction and its product in one launch.  Every block sums
+// the update kernel's np partials of r.D^-1.r, r.r and chi.r itself (same
+// order everywhere): cc = (chi.r)/E, (r.z)_new = r.D^-1.r + cc (chi.r), beta =
+// (r.z)_new / scal[prv]; block 0 publishes cc in scal[S_CC], (r.z)_new in
+// scal[cur] and r.r in scal[S_RR].  The operands of a row's product do not
+// depend on these scalars, so the first row's loads are issued before the sums
+// and their latency overlaps them.  A row group forms the direction of every
+// column it touches with the same operations as the column's own row, which
+// alone stores it (p_old and p_new are two buffers); q = K p_new and partials
+// of p_new . q.
+template <int L>
+__global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, const int32_t* ecol, const double* zd,
+                                                          const uint8_t* chif, const double* p_old, double* p_new,
+                                                          double* q, const double* part, int np, double* scal,
+                                                          int cur, int prv, int first, long nrows,
+                                                          double* part_pap) {
   __shared__ double sh[8];
   __shared__ double bc[3];
+  const int lane = threadIdx.x % L;
+  const long groups = (long)gridDim.x * (blockDim.x / L);
+  long row = (long)blockIdx.x * (blockDim.x / L) + threadIdx.x / L;
+  EllRow e;
+  ell_row_load<L>(e, row, lane, nrows, eval, ecol, zd, chif, p_old);
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) {
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
     s1 += part[i];
     s2 += part[kRedBlocks + i];
     s3 += part[2 * kRedBlocks + i];
@@ -375,17 +489,30 @@ __global__ void cg_p_kernel(double* p, const double* r, const double* dinv, cons
   const double E = scal[S_E];
   const double cc = (E > 0.0) ? bc[2] / E : 0.0;
   const double rz_new = bc[0] + cc * bc[2];
-  const double rz = scal[ra];
+  const double rz = first ? 0.0 : scal[prv];
   const double beta = (!first && rz != 0.0) ? rz_new / rz : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     scal[S_CC] = cc;
-    scal[rb] = rz_new;
+    scal[cur] = rz_new;
     scal[S_RR] = bc[1];
   }
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const double zi = dinv[i] * r[i] + (chi(i, nd, mask) ? cc : 0.0);
-    p[i] = first ? zi : zi + beta * p[i];
+  double acc = 0.0;
+  for (; row < nrows; row += groups) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kEllSlots; ++k) s += e.val[k] * cg_dir(e.zd[k], e.po[k], e.cf[k], cc, beta);
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, L);
+    if (lane == 0) {
+      const double pi = cg_dir(e.zd_own, e.po_own, e.cf_own, cc, beta);
+      p_new[row] = pi;
+      q[row] = s;
+      acc += pi * s;
+    }
+    ell_row_load<L>(e, row + groups, lane, nrows, eval, ecol, zd, chif, p_old);
   }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part_pap[blockIdx.x] = t;
 }
 
 __global__ void precond_kernel(double* z, const double* r, const double* dinv, long n) {
@@ -482,6 +609,13 @@ struct Work {
   double *K = nullptr, *Kmp = nullptr, *R = nullptr, *Rmp = nullptr, *kt = nullptr, *ktmp = nullptr;
   double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double *v = nullptr, *t = nullptr, *r0 = nullptr, *dinv = nullptr;
+  // Krylov iterations (allocated on the first solve): the ELL copy of the
+  // masked matrix (ell_lanes lanes per row), the second direction buffer,
+  // D^-1 r and the chi flags of the solve's mask
+  int ell_lanes = 0;
+  int32_t* ell_col = nullptr;
+  double *ell_val = nullptr, *p2 = nullptr, *zd = nullptr;
+  uint8_t* chif = nullptr;
   double *ub = nullptr, *phib = nullptr;
   double *part = nullptr, *scal = nullptr, *hscal = nullptr;
   uint8_t* mask = nullptr;
@@ -513,7 +647,7 @@ void release_newton_work(gedmg_ctx* c) {
       Work& w = h[i]->w;
       void* ptrs[] = {w.K, w.Kmp, w.R, w.Rmp, w.kt, w.ktmp, w.b, w.x, w.r, w.z, w.p, w.q,
                       w.v, w.t, w.r0, w.dinv, w.ub, w.phib, w.part, w.scal, w.mask,
-                      w.al_uh, w.al_dp, w.al_a, w.al_y};
+                      w.al_uh, w.al_dp, w.al_a, w.al_y, w.ell_col, w.ell_val, w.p2, w.zd, w.chif};
       for (void* p : ptrs)
         if (p) (void)hipFree(p);
       if (w.hscal) (void)hipHostFree(w.hscal);
@@ -544,7 +678,7 @@ int ensure_work(gedmg_ctx* c, Work** out) {
       al(&w.z, w.ndof) || al(&w.p, w.ndof) || al(&w.q, w.ndof) || al(&w.v, w.ndof) ||
       al(&w.t, w.ndof) || al(&w.r0, w.ndof) || al(&w.dinv, w.ndof) ||
       al(&w.ub, (long)c->dim * c->n_nodes) || al(&w.phib, c->n_nodes) ||
-      al(&w.part, 4 * kRedBlocks) || al(&w.scal, S_NSLOTS) ||
+      al(&w.part, 3 * kRedBlocks + kEllMaxBlocks) || al(&w.scal, S_NSLOTS) ||
       hipMalloc((void**)&w.mask, std::max(w.ndof, 1L)) ||
       hipHostMalloc((void**)&w.hscal, sizeof(double) * S_NSLOTS, 0)) {
     c->err = "device allocation for the Newton workspace failed";
@@ -557,6 +691,85 @@ int ensure_work(gedmg_ctx* c, Work** out) {
 
 int grid_for(long n) { return (int)std::min<long>(kRedBlocks, (n + kThreads - 1) / kThreads); }
 
+// The ELL column layout of the CSR pattern, built on the first Krylov solve:
+// the lane count is the smallest power of two whose kEllSlots slots per lane
+// hold the longest row.
+int ensure_ell(gedmg_ctx* c, Work& w) {
+  if (w.ell_col) return GEDMG_OK;
+  const long n = w.ndof;
+  std::vector<int32_t> rp(n + 1);
+  GH(hipMemcpy(rp.data(), c->drowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+  int longest = 1;
+  for (long i = 0; i < n; ++i) longest = std::max(longest, rp[i + 1] - rp[i]);
+  int L = 1;
+  while (L * kEllSlots < longest && L < kEllMaxLanes) L *= 2;
+  if (L * kEllSlots < longest) {
+    c->err = "a row of the sparse pattern is longer than the Krylov solver's limit of " +
+             std::to_string(kEllMaxLanes * kEllSlots) + " entries";
+    return GEDMG_E_ARG;
+  }
+  const long slots = (long)L * kEllSlots * std::max(n, 1L);
+  if (hipMalloc((void**)&w.ell_col, sizeof(int32_t) * slots) || hipMalloc((void**)&w.ell_val, sizeof(double) * slots) ||
+      hipMalloc((void**)&w.p2, sizeof(double) * std::max(n, 1L)) ||
+      hipMalloc((void**)&w.zd, sizeof(double) * std::max(n, 1L)) || hipMalloc((void**)&w.chif, std::max(n, 1L))) {
+    c->err = "device allocation for the Krylov workspace failed";
+    for (void* q : {(void*)w.ell_col, (void*)w.ell_val, (void*)w.p2, (void*)w.zd, (void*)w.chif})
+      if (q) (void)hipFree(q);
+    w.ell_col = nullptr;
+    w.ell_val = w.p2 = w.zd = nullptr;
+    w.chif = nullptr;
+    return GEDMG_E_NOMEM;
+  }
+  w.ell_lanes = L;
+  if (n > 0)
+    hipLaunchKernelGGL(ell_cols_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->drowptr, c->dcol, n, L,
+                       w.ell_col);
+  GH(hipGetLastError());
+  return GEDMG_OK;
+}
+
+// grid of the ELL kernels: one row group per row, at most kEllMaxBlocks blocks
+int ell_grid(const Work& w) {
+  const long groups_per_block = kThreads / w.ell_lanes;
+  return (int)std::max(1L, std::min<long>(kEllMaxBlocks, (w.ndof + groups_per_block - 1) / groups_per_block));
+}
+
+#define ELL_LAUNCH(KERNEL, L, GRID, ...)                                                                   \
+  switch (L) {                                                                                             \
+    case 1: hipLaunchKernelGGL((KERNEL<1>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 2: hipLaunchKernelGGL((KERNEL<2>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 4: hipLaunchKernelGGL((KERNEL<4>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 16: hipLaunchKernelGGL((KERNEL<16>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
+    case 32: hipLaunchKernelGGL((KERNEL<32>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((KERNEL<64>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
+  }
+
+// The ELL values of the masked matrix K and the chi flags of w.mask (at the
+// start of every Krylov solve).
+int ell_pack(gedmg_ctx* c, Work& w, const double* K) {
+  int rc = ensure_ell(c, w);
+  if (rc) return rc;
+  if (w.ndof > 0)
+    hipLaunchKernelGGL(ell_pack_kernel, dim3((w.ndof + 255) / 256), dim3(256), 0, c->stream, K, c->drowptr, w.mask,
+                       c->dim + 1, w.ndof, w.ell_lanes, w.ell_val, w.chif);
+  GH(hipGetLastError());
+  return GEDMG_OK;
+}
+
+// y = K x with the ELL copy of the last ell_pack, scal[slot] = w . y
+int ell_spmv(gedmg_ctx* c, Work& w, const double* x, double* y, const double* wv, int slot) {
+  const int gs = ell_grid(w);
+  double* part = w.part + 3 * kRedBlocks;
+  ELL_LAUNCH(ell_spmv_kernel, w.ell_lanes, gs, w.ell_val, w.ell_col, x, y, wv, w.ndof, part);
+  GH(hipGetLastError());
+  if (slot >= 0) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, part, w.scal, slot, -1, gs);
+    GH(hipGetLastError());
+  }
+  return GEDMG_OK;
+}
+
 // y = K x, scal[slot] = w . y
 int spmv(gedmg_ctx* c, Work& w, const double* K, const double* x, double* y, const double* wv, int slot) {
   const int G = c->dim == 3 ? 32 : 16;
@@ -568,22 +781,9 @@ int spmv(gedmg_ctx* c, Work& w, const double* K, const double* x, double* y, con
                        c->dcol, x, y, wv, w.ndof, w.part);
   GH(hipGetLastError());
   if (slot >= 0) {
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, slot, -1);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, slot, -1, kRedBlocks);
     GH(hipGetLastError());
   }
-  return GEDMG_OK;
-}
-
-// y = K x and per-block partials of wv . y into part (no reduction launch)
-int spmv_part(gedmg_ctx* c, Work& w, const double* K, const double* x, double* y, const double* wv, double* part) {
-  const int G = c->dim == 3 ? 32 : 16;
-  if (G == 32)
-    hipLaunchKernelGGL((spmv_dot_kernel<32>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, K, c->drowptr,
-                       c->dcol, x, y, wv, w.ndof, part);
-  else
-    hipLaunchKernelGGL((spmv_dot_kernel<16>), dim3(kRedBlocks), dim3(kThreads), 0, c->stream, K, c->drowptr,
-                       c->dcol, x, y, wv, w.ndof, part);
-  GH(hipGetLastError());
   return GEDMG_OK;
 }
 
@@ -591,7 +791,7 @@ int dot2(gedmg_ctx* c, Work& w, const double* a, const double* b, const double* 
          int s1, int s2) {
   hipLaunchKernelGGL(dot2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, a, b, cc, d, w.ndof, w.part);
   GH(hipGetLastError());
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, s1, s2);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, s1, s2, kRedBlocks);
   GH(hipGetLastError());
   return GEDMG_OK;
 }
@@ -602,7 +802,7 @@ int read_scalars(gedmg_ctx* c, Work& w);
 int wdot(gedmg_ctx* c, Work& w, const double* a, const double* b, double w2, double* out) {
   hipLaunchKernelGGL(wdot_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, a, b, w.ndof, c->dim + 1, w2,
                      w.part);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_TT, -1);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_TT, -1, kRedBlocks);
   GH(hipGetLastError());
   const int rc = read_scalars(c, w);
   if (rc) return rc;
@@ -619,28 +819,35 @@ int read_scalars(gedmg_ctx* c, Work& w) {
 // Solve K x = b (CG with the Jacobi + coarse preconditioner; BiCGStab with
 // Jacobi on non-positive curvature).  K is the masked matrix and w.mask the
 // Dirichlet mask of this solve.  Returns iterations in *its.
-// CG in three launches per iteration (the sparse product with partials of
-// p.q, the update, the p update); the host polls the residual adaptively (each
-// poll stalls the stream, so the next one is placed at 70 % of the iterations
-// that the observed decay rate still needs, 8 to 128 ahead).
+// CG in two launches per iteration: the new search direction with its product
+// from the ELL copy (and partials of p.q), then the update (and partials of
+// r.D^-1.r, r.r and chi.r).  The host polls the residual adaptively (each poll
+// stalls the stream, so the next one is placed at 70 % of the iterations that
+// the observed decay rate still needs, 8 to 128 ahead).  The ELL copy of K is
+// packed by the caller.
 // Sets *curvature on non-positive curvature; *bb_out receives b.b.
 int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int* its, bool* curvature,
              double* bb_out) {
   const long n = w.ndof;
   const int gr = kRedBlocks;
+  const int gu = grid_for(n);
+  const int gs = ell_grid(w);
   const int nd = c->dim + 1;
+  double* part_pap = w.part + 3 * kRedBlocks;
+  double* pbuf[2] = {w.p, w.p2};
   int rc;
   *its = 0;
   *curvature = false;
   GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
+  GH(hipMemsetAsync(w.p, 0, sizeof(double) * n, c->stream));  // p_old of the first iteration
   GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
   GH(hipMemcpyAsync(w.r, w.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
   hipLaunchKernelGGL(coarse_energy_kernel, dim3(gr), dim3(kThreads), 0, c->stream, K, c->drowptr, c->dcol,
                      w.mask, nd, n, w.part);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_E, -1);
-  hipLaunchKernelGGL(cg_init_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.r, w.dinv, w.mask, nd, n, w.part);
-  hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.dinv, w.mask, nd, w.part,
-                     w.scal, S_RZ, S_RZ, 1, n);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_E, -1, kRedBlocks);
+  hipLaunchKernelGGL(cg_init_kernel, dim3(gu), dim3(kThreads), 0, c->stream, w.r, w.dinv, w.chif, n, w.part, w.zd);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part + kRedBlocks, w.scal, S_RR, -1,
+                     gu);
   GH(hipGetLastError());
   if ((rc = read_scalars(c, w))) return rc;
   const double bb = w.hscal[S_RR];
@@ -652,16 +859,21 @@ int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, in
   int next_poll = check, prev_it = 0;
   double prev_rr = bb;
   for (int it = 1; it <= max_it; ++it) {
-    const int ra = (it & 1) ? S_RZ : S_RZNEW, rb = (it & 1) ? S_RZNEW : S_RZ;
-    double* part_pap = w.part + 3 * kRedBlocks;
-    if ((rc = spmv_part(c, w, K, w.p, w.q, w.p, part_pap))) return rc;
-    hipLaunchKernelGGL(cg_update_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.x, w.r, w.p, w.q, w.dinv,
-                       w.mask, nd, w.scal, ra, n, part_pap, w.part);
-    hipLaunchKernelGGL(cg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.dinv, w.mask, nd, w.part,
-                       w.scal, ra, rb, 0, n);
+    // (r.z) of this iteration's direction goes to slot cur; the previous one is in prv
+    const int cur = (it & 1) ? S_RZ : S_RZNEW, prv = (it & 1) ? S_RZNEW : S_RZ;
+    double* p_old = pbuf[(it - 1) & 1];
+    double* p_new = pbuf[it & 1];
+    ELL_LAUNCH(cg_dir_spmv_kernel, w.ell_lanes, gs, w.ell_val, w.ell_col, w.zd, w.chif, p_old, p_new, w.q, w.part,
+               gu, w.scal, cur, prv, (int)(it == 1), n, part_pap);
+    hipLaunchKernelGGL(cg_update_kernel, dim3(gu), dim3(kThreads), 0, c->stream, w.x, w.r, p_new, w.q, w.dinv,
+                       w.chif, w.scal, cur, n, part_pap, gs, w.part, w.zd);
     GH(hipGetLastError());
     *its = it;
     if (it == next_poll || it == max_it) {
+      // r.r of the updated residual
+      hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part + kRedBlocks, w.scal, S_RR,
+                         -1, gu);
+      GH(hipGetLastError());
       if ((rc = read_scalars(c, w))) return rc;
       if (w.hscal[S_FLAG] != 0.0) { *curvature = true; return GEDMG_OK; }
       const double rr = w.hscal[S_RR];
@@ -688,10 +900,14 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
   const int gr = kRedBlocks;
   *its = 0;
   double bb = 0.0;
+  {
+    const int rcp = ell_pack(c, w, K);
+    if (rcp) return rcp;
+  }
   if (method == 1) {  // BiCGStab requested (non-symmetric tangents)
     hipLaunchKernelGGL(dot2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, w.b, w.b, nullptr, nullptr,
                        n, w.part);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_BB, -1);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_BB, -1, kRedBlocks);
     GH(hipGetLastError());
     int rc0 = read_scalars(c, w);
     if (rc0) return rc0;
@@ -736,16 +952,16 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
     hipLaunchKernelGGL(bicg_scalars_kernel, dim3(1), dim3(1), 0, c->stream, w.scal, 0);
     hipLaunchKernelGGL(bicg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.v, w.scal, n);
     hipLaunchKernelGGL(precond_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.z, w.p, w.dinv, n);  // phat
-    if ((rc = spmv(c, w, K, w.z, w.v, w.r0, S_VR))) return rc;                                            // v = K phat
+    if ((rc = ell_spmv(c, w, w.z, w.v, w.r0, S_VR))) return rc;                                            // v = K phat
     hipLaunchKernelGGL(bicg_scalars_kernel, dim3(1), dim3(1), 0, c->stream, w.scal, 1);
     hipLaunchKernelGGL(bicg_s_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.r, w.v, w.scal, n);     // s in r
     hipLaunchKernelGGL(precond_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.q, w.r, w.dinv, n);  // shat
-    if ((rc = spmv(c, w, K, w.q, w.t, nullptr, -1))) return rc;                                         // t = K shat
+    if ((rc = ell_spmv(c, w, w.q, w.t, nullptr, -1))) return rc;                                         // t = K shat
     if ((rc = dot2(c, w, w.t, w.t, w.t, w.r, S_TT, S_TS))) return rc;
     hipLaunchKernelGGL(bicg_scalars_kernel, dim3(1), dim3(1), 0, c->stream, w.scal, 2);
     hipLaunchKernelGGL(bicg_update_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.x, w.r, w.z, w.q, w.t,
                        w.scal, n, w.part);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_RR, -1);
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_RR, -1, kRedBlocks);
     GH(hipGetLastError());
     *its = cg_its + it;
     if (it % check == 0 || it == max_it) {
@@ -760,7 +976,7 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
 }
 
 double sum_partials_host(gedmg_ctx* c, Work& w, int* rc) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_FLAG + 1, -1);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_FLAG + 1, -1, kRedBlocks);
   *rc = read_scalars(c, w);
   return w.hscal[S_FLAG + 1];
 }

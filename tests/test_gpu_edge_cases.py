@@ -14,6 +14,7 @@ from gpu_common import rel_err, state, sync, to_scipy
 
 pytestmark = pytest.mark.gpu
 E_ARG, E_SHAPE, E_LOCAL_NOCONV, E_JNONPOS = -1, -2, -4, -9
+E_NEWTON_NOCONV = -5
 
 
 @pytest.fixture(scope="module")
@@ -239,23 +240,58 @@ def test_arclength_rejects_invalid_arguments(G):
     ctx.close()
 
 
-def test_failed_newton_step_backtracks_and_restores_fields(G):
-    """A load step that cannot be solved fails cleanly.  The 20^3 heterogeneous
-    cube with every boundary node on its seeded field (random phi against
-    beta_d = 1000 drives the interior into damage at once) makes the Newton
-    iteration diverge: its corrections invert elements, each is halved up to
-    12 times, and the step then returns GEDMG_E_JNONPOS with u, phi and kappa
-    exactly as they were passed in."""
+def test_diverging_newton_step_backtracks(G):
+    """A load step whose Newton corrections invert elements.  The 20^3
+    heterogeneous cube with every boundary node on its seeded field (random phi
+    against beta_d = 1000 drives the interior into damage at once) sends the
+    Newton iteration far from the start: corrections that leave a point with
+    det F <= 0 are halved, up to 12 times in the step.  Whether the iteration
+    then recovers and converges or runs out of halvings depends on the rounding
+    of every Krylov solve on the way, so both outcomes are accepted: a
+    converged step meets the residual test, and a failed one reports
+    GEDMG_E_JNONPOS after all 12 halvings (or the Newton iteration limit) with
+    u, phi and kappa exactly as they were passed in."""
     case = W.make_case(4, n=20)
     bd, bv = W.boundary_field_bc(case)
     ctx = G.Context.from_case(case)
     u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
     u0, p0, k0 = u.clone(), phi.clone(), kap.clone()
     print("[edge] diverging Newton step on the 20^3 heterogeneous cube", flush=True)
+    atol = 1e-9 * np.sqrt(case.mesh.ndof)
     rep = ctx.newton_step(u, phi, kap, bd, bv, raise_on_error=False, max_newton=40, newton_rtol=1e-10,
-                          newton_atol=1e-9 * np.sqrt(case.mesh.ndof))
+                          newton_atol=atol)
     sync()
     print(f"  status {rep['status']}, iterations {rep['newton_iters']}, backtracks {rep['backtracks']}", flush=True)
-    assert rep["status"] == E_JNONPOS and rep["backtracks"] == 12
+    assert rep["backtracks"] >= 1
+    if rep["status"] == 0:
+        if rep["newton_iters"] < 32:  # the report keeps the first 32 residual norms
+            assert rep["res_norm"][-1] <= max(atol, 1e-10 * max(1.0, rep["res_norm"][0]))
+    else:
+        assert rep["status"] in (E_JNONPOS, E_NEWTON_NOCONV)
+        if rep["status"] == E_JNONPOS:
+            assert rep["backtracks"] == 12
+        assert torch.equal(u, u0) and torch.equal(phi, p0) and torch.equal(kap, k0)
+    ctx.close()
+
+
+def test_newton_step_from_an_inverted_state_fails_and_restores_fields(G):
+    """Boundary values that invert the elements at the boundary (u_x = -2 X_1 on
+    every boundary node: F_11 = -1 there) leave the step nothing to halve: the
+    first assembly reports det F <= 0, and the step returns GEDMG_E_JNONPOS
+    without a correction, with u, phi and kappa exactly as they were passed in
+    (the boundary values it wrote are taken back)."""
+    case = W.make_case(4, n=6)
+    m = case.mesh
+    nodes = W.boundary_nodes(m)
+    bd = (nodes * (m.dim + 1)).astype(np.int32)  # u_x of every boundary node
+    bv = -2.0 * m.X[0, nodes]
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    u0, p0, k0 = u.clone(), phi.clone(), kap.clone()
+    print("[edge] Newton step from an inverted boundary state, 6^3 cube", flush=True)
+    rep = ctx.newton_step(u, phi, kap, bd, bv, raise_on_error=False)
+    sync()
+    print(f"  status {rep['status']}, iterations {rep['newton_iters']}, backtracks {rep['backtracks']}", flush=True)
+    assert rep["status"] == E_JNONPOS and rep["backtracks"] == 0
     assert torch.equal(u, u0) and torch.equal(phi, p0) and torch.equal(kap, k0)
     ctx.close()
