@@ -328,12 +328,26 @@ __device__ __forceinline__ double block_total(const double* part, int np, double
   return *bc;
 }
 
-// x += alpha p, r -= alpha q, zd = D^-1 r; partials of r.D^-1.r, r.r and chi.r
+// x += alpha p, r -= alpha q, zd = D^-1 r; partials of r.D^-1.r, r.r and chi.r.
+// The vector operands of the first entry do not depend on alpha and are loaded
+// before the block sums the partials of p.q.
 __global__ void cg_update_kernel(double* x, double* r, const double* p, const double* Ap, const double* dinv,
                                  const uint8_t* chif, double* scal, int ra, long n, const double* part_pap,
                                  int npap, double* part, double* zd) {
   __shared__ double sh[8];
   __shared__ double bc;
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long stride = (long)gridDim.x * blockDim.x;
+  double xi = 0.0, ri = 0.0, pi = 0.0, qi = 0.0, di = 0.0;
+  uint8_t ci = 0;
+  if (i < n) {
+    xi = x[i];
+    ri = r[i];
+    pi = p[i];
+    qi = Ap[i];
+    di = dinv[i];
+    ci = chif[i];
+  }
   const double pap = block_total(part_pap, npap, sh, &bc);
   const double alpha = (pap > 0.0) ? scal[ra] / pap : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -341,15 +355,24 @@ __global__ void cg_update_kernel(double* x, double* r, const double* p, const do
     if (!(pap > 0.0)) scal[S_FLAG] = 1.0;  // non-positive curvature
   }
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * Ap[i];
-    r[i] = ri;
-    const double zi = dinv[i] * ri;
+  for (; i < n; i += stride) {
+    x[i] = xi + alpha * pi;
+    const double rn = ri - alpha * qi;
+    r[i] = rn;
+    const double zi = di * rn;
     zd[i] = zi;
-    s1 += ri * zi;
-    s2 += ri * ri;
-    if (chif[i]) s3 += ri;
+    s1 += rn * zi;
+    s2 += rn * rn;
+    if (ci) s3 += rn;
+    const long j = i + stride;
+    if (j < n) {
+      xi = x[j];
+      ri = r[j];
+      pi = p[j];
+      qi = Ap[j];
+      di = dinv[j];
+      ci = chif[j];
+    }
   }
   double t = block_sum(s1, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
