@@ -25,7 +25,7 @@ constexpr int kRedBlocks = 512;  // blocks of every reduction kernel
 // lane, 1 to kEllMaxLanes lanes per row, enough for the longest row.
 constexpr int kEllSlots = 27;
 constexpr int kEllMaxLanes = 64;
-constexpr int kEllMaxBlocks = 2048;  // grid cap of the ELL products (partials)
+constexpr int kEllMaxBlocks = 8192;  // grid cap of the ELL products (partials)
 constexpr int kMaxBacktracks = 12;  // halvings of one Newton correction
 constexpr int kThreads = 256;
 
@@ -481,7 +481,7 @@ __device__ __forceinline__ double cg_dir(double zd, double po, uint8_t cf, doubl
 // column it touches with the same operations as the column's own row, which
 // alone stores it (p_old and p_new are two buffers); q = K p_new and partials
 // of p_new . q.
-template <int L>
+template <int L, bool LOOP>
 __global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, const int32_t* ecol, const double* zd,
                                                           const uint8_t* chif, const double* p_old, double* p_new,
                                                           double* q, const double* part, int np, double* scal,
@@ -520,6 +520,8 @@ __global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, co
     scal[S_RR] = bc[1];
   }
   double acc = 0.0;
+  // LOOP = false: the grid has a row group for every row (fewer live registers
+  // than the loop's prefetch of the next row, two waves per SIMD instead of one)
   for (; row < nrows; row += groups) {
     double s = 0.0;
 #pragma unroll
@@ -532,6 +534,7 @@ __global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, co
       q[row] = s;
       acc += pi * s;
     }
+    if (!LOOP) break;
     ell_row_load<L>(e, row + groups, lane, nrows, eval, ecol, zd, chif, p_old);
   }
   const double t = block_sum(acc, sh);
@@ -752,6 +755,7 @@ int ensure_ell(gedmg_ctx* c, Work& w) {
 }
 
 // grid of the ELL kernels: one row group per row, at most kEllMaxBlocks blocks
+// (beyond that the row groups loop over rows)
 int ell_grid(const Work& w) {
   const long groups_per_block = kThreads / w.ell_lanes;
   return (int)std::max(1L, std::min<long>(kEllMaxBlocks, (w.ndof + groups_per_block - 1) / groups_per_block));
@@ -766,6 +770,16 @@ int ell_grid(const Work& w) {
     case 16: hipLaunchKernelGGL((KERNEL<16>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
     case 32: hipLaunchKernelGGL((KERNEL<32>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
     default: hipLaunchKernelGGL((KERNEL<64>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
+  }
+#define ELL_LAUNCH_T(KERNEL, L, T, GRID, ...)                                                                   \
+  switch (L) {                                                                                             \
+    case 1: hipLaunchKernelGGL((KERNEL<1, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 2: hipLaunchKernelGGL((KERNEL<2, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 4: hipLaunchKernelGGL((KERNEL<4, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 8: hipLaunchKernelGGL((KERNEL<8, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 16: hipLaunchKernelGGL((KERNEL<16, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
+    case 32: hipLaunchKernelGGL((KERNEL<32, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((KERNEL<64, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
   }
 
 // The ELL values of the masked matrix K and the chi flags of w.mask (at the
@@ -855,6 +869,7 @@ int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, in
   const int gr = kRedBlocks;
   const int gu = grid_for(n);
   const int gs = ell_grid(w);
+  const bool loop = (long)gs * (kThreads / w.ell_lanes) < n;
   const int nd = c->dim + 1;
   double* part_pap = w.part + 3 * kRedBlocks;
   double* pbuf[2] = {w.p, w.p2};
@@ -886,8 +901,13 @@ int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, in
     const int cur = (it & 1) ? S_RZ : S_RZNEW, prv = (it & 1) ? S_RZNEW : S_RZ;
     double* p_old = pbuf[(it - 1) & 1];
     double* p_new = pbuf[it & 1];
-    ELL_LAUNCH(cg_dir_spmv_kernel, w.ell_lanes, gs, w.ell_val, w.ell_col, w.zd, w.chif, p_old, p_new, w.q, w.part,
-               gu, w.scal, cur, prv, (int)(it == 1), n, part_pap);
+    if (loop) {
+      ELL_LAUNCH_T(cg_dir_spmv_kernel, w.ell_lanes, true, gs, w.ell_val, w.ell_col, w.zd, w.chif, p_old, p_new, w.q,
+                   w.part, gu, w.scal, cur, prv, (int)(it == 1), n, part_pap);
+    } else {
+      ELL_LAUNCH_T(cg_dir_spmv_kernel, w.ell_lanes, false, gs, w.ell_val, w.ell_col, w.zd, w.chif, p_old, p_new, w.q,
+                   w.part, gu, w.scal, cur, prv, (int)(it == 1), n, part_pap);
+    }
     hipLaunchKernelGGL(cg_update_kernel, dim3(gu), dim3(kThreads), 0, c->stream, w.x, w.r, p_new, w.q, w.dinv,
                        w.chif, w.scal, cur, n, part_pap, gs, w.part, w.zd);
     GH(hipGetLastError());
