@@ -10,7 +10,8 @@
   the GPU's kappa_trial.  Tolerance as in the small-mesh parity tests: 1e-12
   norm-wise per output.
 - The 32x32x8 Hex8 box through its 10 Newton load steps, against the affine
-  closed form that holds at any mesh size.
+  closed form that holds at any mesh size, and the first step of the same box
+  at 64x64x32 (more rows than one Krylov launch has row groups).
 - The 256^2 notched Q4 plate through its 40 steps with BF16 / FP16 tangents,
   against the FP64 path.
 - The 128^2 Q4 load-path adjoint, against a directional central difference.
@@ -123,6 +124,38 @@ def test_full_size_box_newton_path_matches_closed_form():
         kref = float(model.yld(model.energy(Fn))[0])
         assert np.abs(pg - kref).max() < 1e-6 * max(1.0, kref)
         assert np.abs(kg - kref).max() < 1e-6 * max(1.0, kref)
+    ctx.close()
+
+
+def test_large_box_newton_step_matches_closed_form():
+    """The box at 64x64x32 Hex8 elements (131072 elements, 557700 dofs): more
+    rows than the Krylov kernels' grid covers with one row group each, so the
+    CG direction kernel runs its row loop.  The first affine stretch step
+    against the same closed form as the 32x32x8 box."""
+    from paper_2604_03411_amd import gedmg as G
+    case = W.make_case(2, n=64, nz=32)
+    m = case.mesh
+    assert m.ndof > 8192 * 64  # rows beyond one row group of 4 lanes per row per thread group
+    print(f"[large box] hex8 {m.n_elems} elements, {m.ndof} dofs, step 1", flush=True)
+    ctx = G.Context.from_case(case)
+    u, phi, kap = ctx.fields(case.u, case.phi, case.kappa)
+    model = fem.Model(case)
+    lam = case.extra["stretch"]
+    X = np.asarray(m.X)
+    n = 1
+    u.copy_(torch.as_tensor(W.affine_stretch_guess(case, n), device=ctx.dev))
+    bd, bv = W.affine_stretch_bc(case, n)
+    rep = ctx.newton_step(u, phi, kap, bd, bv, "fp64", reaction_dofs=W.reaction_dofs(case),
+                          newton_rtol=0.0, newton_atol=1e-12, krylov_rtol=1e-13)
+    sync()
+    print(f"  iters {rep['newton_iters']} krylov {rep['krylov_iters']} res {rep['res_norm'][-1]:.2e}", flush=True)
+    s_ = n / case.n_steps
+    ug, pg, kg = u.cpu().numpy(), phi.cpu().numpy(), kap.cpu().numpy()
+    assert np.abs(ug - s_ * (lam[:, None] - 1.0) * X).max() < 1e-9
+    Fn = torch.diag(torch.tensor(1.0 + s_ * (lam - 1.0), dtype=torch.float64))[None]
+    kref = float(model.yld(model.energy(Fn))[0])
+    assert np.abs(pg - kref).max() < 1e-6 * max(1.0, kref)
+    assert np.abs(kg - kref).max() < 1e-6 * max(1.0, kref)
     ctx.close()
 
 
