@@ -2,11 +2,12 @@
 // every global iteration, tangent contributions of kappa included; each step
 // starts from the caller's predictor built on the last converged solution)
 // with a preconditioned Krylov solve per iteration.  The CG preconditioner is
-// Jacobi plus a one-vector coarse correction on the uniform damage field
-// (M^-1 r = D^-1 r + chi (chi . r) / (chi . K chi), chi = 1 on the free damage
-// dofs): once the points yield, the damage block's only stiffness against a
-// uniform phi is beta_d (1 - d kappa / d phi), orders of magnitude below the
-// rest of the spectrum, and this mode would otherwise set the CG iteration count.
+// two-level: Jacobi plus a coarse correction on node aggregates (piecewise
+// constant per aggregate and dof component), whose span holds the uniform
+// damage field: once the points yield, the damage block's only stiffness
+// against a uniform phi is beta_d (1 - d kappa / d phi), orders of magnitude
+// below the rest of the spectrum, and this mode and the aggregates' smooth
+// modes would otherwise set the CG iteration count.
 //
 // Sparse kernels are deterministic: fixed grids, per-block partial sums in a
 // fixed order, one-block final reductions; Krylov scalars stay on the device
@@ -26,6 +27,11 @@ constexpr int kRedBlocks = 512;  // blocks of every reduction kernel
 constexpr int kEllSlots = 27;
 constexpr int kEllMaxLanes = 64;
 constexpr int kEllMaxBlocks = 8192;  // grid cap of the ELL products (partials)
+// Two-level preconditioner: at most kCoarseMax coarse dofs (the dense inverse
+// is formed in LDS), and the aggregate-aligned update kernel's grid.
+constexpr int kCoarseMax = 128;
+constexpr int kUpdMaxBlocks = 1024;
+constexpr int kUpdTailMax = 640;  // update blocks whose partials the tail stages in LDS
 constexpr int kMaxBacktracks = 12;  // halvings of one Newton correction
 constexpr int kThreads = 256;
 
@@ -47,13 +53,12 @@ gedmg_solver_opts default_solver_opts() {
 }
 
 // Device scalar slots (doubles).
-// S_FLAG + 1 holds sums read back by the host; S_E = chi . K chi and S_CC =
-// (chi . r) / S_E, the coarse coefficient of the current residual.
+// S_FLAG + 1 holds sums read back by the host, S_FLAG + 2 flags a singular
+// coarse matrix; S_RDR = r.D^-1.r and S_RZC = r_c . A_c^-1 r_c of the current
+// CG residual (r.z = S_RDR + S_RZC).
 enum Slot { S_RZ = 0, S_PAP, S_ALPHA, S_BETA, S_RR, S_BB, S_RHO, S_OMEGA, S_TT, S_TS, S_VR, S_RZNEW,
-            S_FLAG, S_E = 14, S_CC = 15, S_NSLOTS = 16 };
+            S_FLAG, S_RDR = 15, S_RZC = 16, S_NSLOTS = 17 };
 
-// chi_i: free (not Dirichlet) damage dof
-__device__ __forceinline__ bool chi(long i, int nd, const uint8_t* mask) { return (i % nd) == nd - 1 && !mask[i]; }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
 #pragma unroll
@@ -276,45 +281,154 @@ __global__ void reduce_kernel(const double* part, double* scal, int slot, int sl
   }
 }
 
-// ---- CG pieces.  r.z alternates between two slots (ra holds the current
-// value, rb receives the next), so every block forms alpha and beta itself and
-// no single-thread scalar kernel sits between the vector kernels.  z = M^-1 r
-// is never stored: r.z = r.D^-1.r + (chi.r)^2 / E comes out of the partial
-// sums, and the p update forms z on the fly.
+// ---- CG pieces.  The preconditioner is two-level (additive):
+//   M^-1 r = D^-1 r + P A_c^-1 P^T r,   A_c = P^T K P,
+// P the piecewise-constant prolongation from node aggregates (boxes of the
+// mesh's bounding box), one coarse dof per aggregate and dof component, zero on
+// Dirichlet dofs.  The coarse space holds the uniform damage field over the
+// free damage dofs, the soft mode of a yielding tangent (stiffness beta_d
+// (1 - d kappa / d phi), orders of magnitude below the rest of the spectrum),
+// and the aggregates' smooth modes that set Jacobi-CG's iteration count.  A_c
+// (at most kCoarseMax dofs) is assembled and inverted densely at the start of
+// every solve.  z = M^-1 r is never stored: the update kernel leaves D^-1 r
+// and partials, a one-block kernel the coarse correction y_c = A_c^-1 P^T r
+// with the scalars r.D^-1.r, r_c.y_c and r.r, and the direction kernel forms z
+// on the fly.  r.z of the current and of the previous direction alternate
+// between two slots.
 
-// chi . K chi over the masked matrix (rows and columns of free damage dofs)
-__global__ void coarse_energy_kernel(const double* K, const int32_t* rowptr, const int32_t* col,
-                                     const uint8_t* mask, int nd, long nrows, double* part) {
+// A_c from the masked matrix: one block per coarse nonzero sums, in a fixed
+// order, the entries of K whose row and column are free and map to it (seg_e
+// lists them by coarse nonzero, seg_row their rows).
+__global__ __launch_bounds__(256) void coarse_matrix_kernel(const double* K, const int32_t* col,
+                                                            const int32_t* seg_ptr, const int32_t* seg_key,
+                                                            const int32_t* seg_e, const int32_t* seg_row,
+                                                            const uint8_t* mask, double* Ac) {
   __shared__ double sh[8];
-  double acc = 0.0;
-  for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (long)gridDim.x * blockDim.x) {
-    if (!chi(r, nd, mask)) continue;
-    for (int j = rowptr[r]; j < rowptr[r + 1]; ++j)
-      if (chi(col[j], nd, mask)) acc += K[j];
+  const int seg = blockIdx.x;
+  double v = 0.0;
+  for (int k = seg_ptr[seg] + threadIdx.x; k < seg_ptr[seg + 1]; k += blockDim.x) {
+    const int e = seg_e[k];
+    if (!mask[seg_row[k]] && !mask[col[e]]) v += K[e];
   }
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) Ac[seg_key[seg]] = t;
 }
 
-// partial sums of r.D^-1.r, r.r and chi.r; zd = D^-1 r
-__global__ void cg_init_kernel(const double* r, const double* dinv, const uint8_t* chif, long n, double* part,
-                               double* zd) {
-  __shared__ double sh[8];
-  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const double ri = r[i];
-    const double zi = dinv[i] * ri;
-    zd[i] = zi;
-    s1 += ri * zi;
-    s2 += ri * ri;
-    if (chif[i]) s3 += ri;
+// Gauss-Jordan inverse of A_c (nc <= kCoarseMax) with partial pivoting, one
+// block of 1024 threads: thread t owns row t / 8, columns t % 8 + 8 m, in
+// registers.  Rows are not interchanged: column k's pivot is the largest
+// |A[i][k]| over the rows not yet used as pivots (p_k, lowest index on ties),
+// and the in-place elimination then leaves P with A^-1[a][b] =
+// P[p_a][q_b], q the inverse of p.  A coarse dof without free dofs has a zero
+// row and column and gets a unit diagonal.  Writes the transpose of the
+// inverse (for coalesced products); a zero pivot sets scal[S_FLAG + 2] and
+// leaves the coarse correction out (zero inverse).
+__global__ __launch_bounds__(1024) void coarse_invert_kernel(const double* Ac, int nc, double* AinvT, double* scal) {
+  constexpr int M = kCoarseMax / 8;
+  __shared__ double P[kCoarseMax * kCoarseMax];
+  __shared__ double colk[2][kCoarseMax];
+  __shared__ double prow[kCoarseMax];
+  __shared__ int pk[kCoarseMax], qk[kCoarseMax], used[kCoarseMax];
+  __shared__ int piv_row, singular;
+  const int t = threadIdx.x;
+  const int ti = t >> 3, tj = t & 7;
+  const bool own = ti < nc;
+  double a[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int j = tj + 8 * m;
+    a[m] = (own && j < nc) ? Ac[ti * nc + j] : 0.0;
   }
-  double t = block_sum(s1, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-  t = block_sum(s2, sh);
-  if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = t;
-  t = block_sum(s3, sh);
-  if (threadIdx.x == 0) part[2 * kRedBlocks + blockIdx.x] = t;
+  // a coarse dof without free dofs: unit diagonal (its row and column are zero)
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+    if (own && tj + 8 * m == ti && a[m] == 0.0) a[m] = 1.0;
+  if (t < kCoarseMax) used[t] = 0;
+  if (t == 0) singular = 0;
+  __syncthreads();
+  for (int k = 0; k < nc; ++k) {
+    double* ck = colk[k & 1];
+    if (own && tj == (k & 7)) {
+      double v = 0.0;
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        if (m == (k >> 3)) v = a[m];
+      ck[ti] = v;
+    }
+    __syncthreads();
+    if (t < 64) {  // pivot search by one wavefront
+      double bv = -1.0;
+      int bi = nc;
+      for (int i = t; i < nc; i += 64)
+        if (!used[i]) {
+          const double v = fabs(ck[i]);
+          if (v > bv || (v == bv && i < bi)) {
+            bv = v;
+            bi = i;
+          }
+        }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (t == 0) {
+        if (!(bv > 0.0) || bi >= nc) {
+          singular = 1;
+        } else {
+          piv_row = bi;
+          used[bi] = 1;
+          pk[k] = bi;
+          qk[bi] = k;
+        }
+      }
+    }
+    __syncthreads();
+    if (singular) break;
+    const int p = piv_row;
+    const double pivinv = 1.0 / ck[p];
+    if (ti == p) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int j = tj + 8 * m;
+        const double v = (j == k ? 1.0 : a[m]) * pivinv;
+        a[m] = v;
+        if (j < nc) prow[j] = v;
+      }
+    }
+    __syncthreads();
+    if (own && ti != p) {
+      const double f = ck[ti];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int j = tj + 8 * m;
+        if (j < nc) a[m] = (j == k ? 0.0 : a[m]) - f * prow[j];
+      }
+    }
+  }
+  if (singular) {
+    for (int i = t; i < nc * nc; i += blockDim.x) AinvT[i] = 0.0;
+    if (t == 0) scal[S_FLAG + 2] = 1.0;
+    return;
+  }
+  __syncthreads();
+  if (own) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int j = tj + 8 * m;
+      if (j < nc) P[ti * nc + j] = a[m];
+    }
+  }
+  __syncthreads();
+  // A^-1[r][c] = P[p_r][q_c], stored transposed: AinvT[c * nc + r]
+  for (int idx = t; idx < nc * nc; idx += blockDim.x) {
+    const int c = idx / nc, r = idx - c * nc;
+    AinvT[idx] = P[pk[r] * nc + qk[c]];
+  }
 }
 
 // Every block sums the np partials of p.Ap of the sparse product itself (same
@@ -328,58 +442,145 @@ __device__ __forceinline__ double block_total(const double* part, int np, double
   return *bc;
 }
 
-// x += alpha p, r -= alpha q, zd = D^-1 r; partials of r.D^-1.r, r.r and chi.r.
-// The vector operands of the first entry do not depend on alpha and are loaded
-// before the block sums the partials of p.q.
-__global__ void cg_update_kernel(double* x, double* r, const double* p, const double* Ap, const double* dinv,
-                                 const uint8_t* chif, double* scal, int ra, long n, const double* part_pap,
-                                 int npap, double* part, double* zd) {
+// x += alpha p, r -= alpha q, zd = D^-1 r, over the dofs of node aggregates:
+// block b serves aggregate b / sub (its dofs agg_dofs[agg_ptr[a] ..
+// agg_ptr[a + 1]), one sub-block of sub), and leaves partials of r.D^-1.r,
+// r.r and, per component, of r over its dofs (the restriction P^T r).
+// init = 1 leaves x and r as they are (the first residual).  The vector
+// operands of a block's first dof are loaded before its sum of the p.q
+// partials.
+__global__ __launch_bounds__(256) void cg_update_kernel(double* x, double* r, const double* p, const double* q,
+                                                        const double* dinv, double* zd, const int32_t* agg_ptr,
+                                                        const int32_t* agg_dofs, int sub, int nd,
+                                                        const double* part_pap, int npap, double* scal, int cur,
+                                                        int init, double* part, double* partc) {
   __shared__ double sh[8];
   __shared__ double bc;
-  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long stride = (long)gridDim.x * blockDim.x;
+  const int a = blockIdx.x / sub, s = blockIdx.x % sub;
+  const int k_end = agg_ptr[a + 1];
+  const int stride = sub * blockDim.x;
+  int k = agg_ptr[a] + s * blockDim.x + threadIdx.x;
+  int i = k < k_end ? agg_dofs[k] : 0;
   double xi = 0.0, ri = 0.0, pi = 0.0, qi = 0.0, di = 0.0;
-  uint8_t ci = 0;
-  if (i < n) {
-    xi = x[i];
+  if (k < k_end) {
     ri = r[i];
-    pi = p[i];
-    qi = Ap[i];
     di = dinv[i];
-    ci = chif[i];
+    if (!init) {
+      xi = x[i];
+      pi = p[i];
+      qi = q[i];
+    }
   }
-  const double pap = block_total(part_pap, npap, sh, &bc);
-  const double alpha = (pap > 0.0) ? scal[ra] / pap : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    scal[S_PAP] = pap;
-    if (!(pap > 0.0)) scal[S_FLAG] = 1.0;  // non-positive curvature
+  double alpha = 0.0;
+  if (!init) {
+    const double pap = block_total(part_pap, npap, sh, &bc);
+    alpha = (pap > 0.0) ? scal[cur] / pap : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      scal[S_PAP] = pap;
+      if (!(pap > 0.0)) scal[S_FLAG] = 1.0;  // non-positive curvature
+    }
   }
-  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (; i < n; i += stride) {
-    x[i] = xi + alpha * pi;
-    const double rn = ri - alpha * qi;
-    r[i] = rn;
+  double s1 = 0.0, s2 = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  while (k < k_end) {
+    double rn = ri;
+    if (!init) {
+      x[i] = xi + alpha * pi;
+      rn = ri - alpha * qi;
+      r[i] = rn;
+    }
     const double zi = di * rn;
     zd[i] = zi;
     s1 += rn * zi;
     s2 += rn * rn;
-    if (ci) s3 += rn;
-    const long j = i + stride;
-    if (j < n) {
-      xi = x[j];
-      ri = r[j];
-      pi = p[j];
-      qi = Ap[j];
-      di = dinv[j];
-      ci = chif[j];
+    const int comp = i % nd;
+    c0 += comp == 0 ? rn : 0.0;
+    c1 += comp == 1 ? rn : 0.0;
+    c2 += comp == 2 ? rn : 0.0;
+    c3 += comp == 3 ? rn : 0.0;
+    k += stride;
+    if (k < k_end) {
+      i = agg_dofs[k];
+      ri = r[i];
+      di = dinv[i];
+      if (!init) {
+        xi = x[i];
+        pi = p[i];
+        qi = q[i];
+      }
     }
   }
-  double t = block_sum(s1, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-  t = block_sum(s2, sh);
-  if (threadIdx.x == 0) part[kRedBlocks + blockIdx.x] = t;
-  t = block_sum(s3, sh);
-  if (threadIdx.x == 0) part[2 * kRedBlocks + blockIdx.x] = t;
+  // the six sums: wavefront shuffles, then the block's wavefronts in order
+  __shared__ double shv[6][4];
+  double v[6] = {s1, s2, c0, c1, c2, c3};
+#pragma unroll
+  for (int qq = 0; qq < 6; ++qq) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[qq] += __shfl_xor(v[qq], o, 64);
+    if ((threadIdx.x & 63) == 0) shv[qq][threadIdx.x >> 6] = v[qq];
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int qq = threadIdx.x;
+    double tsum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tsum += shv[qq][w];
+    if (qq == 0) part[blockIdx.x] = tsum;
+    else if (qq == 1) part[kUpdMaxBlocks + blockIdx.x] = tsum;
+    else partc[blockIdx.x * 4 + (qq - 2)] = tsum;
+  }
+}
+
+// One block of 1024 threads: the update kernel's nb partials summed in a fixed
+// order into r.D^-1.r (scal[S_RDR]) and r.r (scal[S_RR]), the restriction r_c
+// = P^T r, the coarse correction y_c = A_c^-1 r_c (yc) and r_c.y_c
+// (scal[S_RZC]).  A_c^-1 and the restriction's partials are staged in LDS
+// with coalesced loads first.
+__global__ __launch_bounds__(1024) void coarse_tail_kernel(const double* part, const double* partc, int nb, int sub,
+                                                           int nd, int nc, const double* AinvT, double* scal,
+                                                           double* yc) {
+  __shared__ double Ai[kCoarseMax * kCoarseMax];
+  __shared__ double pc[4 * kUpdTailMax];
+  __shared__ double rcs[kCoarseMax];
+  __shared__ double sh[3][16];
+  const int t = threadIdx.x;
+  for (int i = t; i < nc * nc; i += blockDim.x) Ai[i] = AinvT[i];
+  for (int i = t; i < 4 * nb; i += blockDim.x) pc[i] = partc[i];
+  double S1 = 0.0, S2 = 0.0;
+  for (int b = t; b < nb; b += blockDim.x) {
+    S1 += part[b];
+    S2 += part[kUpdMaxBlocks + b];
+  }
+  __syncthreads();
+  if (t < nc) {
+    const int ag = t / nd, comp = t - ag * nd;
+    double v = 0.0;
+    for (int j = 0; j < sub; ++j) v += pc[(ag * sub + j) * 4 + comp];
+    rcs[t] = v;
+  }
+  __syncthreads();
+  double rzc = 0.0;
+  if (t < nc) {
+    double y = 0.0;
+    for (int j = 0; j < nc; ++j) y += Ai[j * nc + t] * rcs[j];
+    yc[t] = y;
+    rzc = rcs[t] * y;
+  }
+  // the three sums: wavefront shuffles, then the 16 wavefronts in order
+  double v[3] = {S1, S2, rzc};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    if ((t & 63) == 0) sh[q][t >> 6] = v[q];
+  }
+  __syncthreads();
+  if (t == 0) {
+    double T[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < 3; ++q)
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) T[q] += sh[q][w];
+    scal[S_RDR] = T[0];
+    scal[S_RR] = T[1];
+    scal[S_RZC] = T[2];
+  }
 }
 
 // ---- ELL copy of the masked matrix for the Krylov iterations.  Slot s of a
@@ -394,15 +595,16 @@ __global__ void ell_cols_kernel(const int32_t* rowptr, const int32_t* col, long 
     ecol[((long)(s / L) * nrows + row) * L + s % L] = s < len ? col[j0 + s] : (int32_t)row;
 }
 
-// ELL values of K, and the chi flags of this solve's mask
-__global__ void ell_pack_kernel(const double* K, const int32_t* rowptr, const uint8_t* mask, int nd, long nrows,
-                                int L, double* eval, uint8_t* chif) {
+// ELL values of K, and the coarse dof of every free dof (-1 on Dirichlet dofs)
+// for this solve's mask
+__global__ void ell_pack_kernel(const double* K, const int32_t* rowptr, const uint8_t* mask, const int32_t* cmap0,
+                                long nrows, int L, double* eval, int32_t* cmap) {
   const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= nrows) return;
   const int j0 = rowptr[row], len = rowptr[row + 1] - j0;
   for (int s = 0; s < L * kEllSlots; ++s)
     eval[((long)(s / L) * nrows + row) * L + s % L] = s < len ? K[j0 + s] : 0.0;
-  chif[row] = chi(row, nd, mask);
+  cmap[row] = mask[row] ? -1 : cmap0[row];
 }
 
 // y = K x from the ELL copy (L lanes per row) and partials of w . y
@@ -433,17 +635,17 @@ __global__ __launch_bounds__(256) void ell_spmv_kernel(const double* eval, const
 
 // The slots of one row of the ELL copy with every operand of its product that
 // does not depend on this iteration's scalars: column values, and D^-1 r, the
-// previous direction and the chi flag at each column and at the row itself.
+// previous direction and the coarse dof at each column and at the row itself.
 struct EllRow {
   double val[kEllSlots], zd[kEllSlots], po[kEllSlots];
-  uint8_t cf[kEllSlots];
+  int32_t cm[kEllSlots];
   double zd_own, po_own;
-  uint8_t cf_own;
+  int32_t cm_own;
 };
 
 template <int L>
 __device__ __forceinline__ void ell_row_load(EllRow& e, long row, int lane, long nrows, const double* eval,
-                                             const int32_t* ecol, const double* zd, const uint8_t* chif,
+                                             const int32_t* ecol, const double* zd, const int32_t* cmap,
                                              const double* p_old) {
   if (row >= nrows) return;
   int col[kEllSlots];
@@ -457,85 +659,63 @@ __device__ __forceinline__ void ell_row_load(EllRow& e, long row, int lane, long
   for (int k = 0; k < kEllSlots; ++k) {
     e.zd[k] = zd[col[k]];
     e.po[k] = p_old[col[k]];
-    e.cf[k] = chif[col[k]];
+    e.cm[k] = cmap[col[k]];
   }
   e.zd_own = zd[row];
   e.po_own = p_old[row];
-  e.cf_own = chif[row];
+  e.cm_own = cmap[row];
 }
 
-// Entry of the new search direction p = z + beta p_old, z = D^-1 r + cc chi,
-// from the loaded operands.  The first direction is z: beta = 0 and p_old is
-// zeroed at the start of the solve.
-__device__ __forceinline__ double cg_dir(double zd, double po, uint8_t cf, double cc, double beta) {
-  return fma(beta, po, zd + (cf ? cc : 0.0));
+// Entry of the new search direction p = z + beta p_old, z = D^-1 r + P y_c,
+// from the loaded operands (ys: y_c in LDS).  The first direction is z: beta
+// = 0 and p_old is zeroed at the start of the solve.
+__device__ __forceinline__ double cg_dir(double zd, double po, int32_t cm, const double* ys, double beta) {
+  return fma(beta, po, zd + (cm >= 0 ? ys[cm] : 0.0));
 }
 
-// The new search direction and its product in one launch.  Every block sums
-// the update kernel's np partials of r.D^-1.r, r.r and chi.r itself (same
-// order everywhere): cc = (chi.r)/E, (r.z)_new = r.D^-1.r + cc (chi.r), beta =
-// (r.z)_new / scal[prv]; block 0 publishes cc in scal[S_CC], (r.z)_new in
-// scal[cur] and r.r in scal[S_RR].  The operands of a row's product do not
-// depend on these scalars, so the first row's loads are issued before the sums
-// and their latency overlaps them.  A row group forms the direction of every
-// column it touches with the same operations as the column's own row, which
-// alone stores it (p_old and p_new are two buffers); q = K p_new and partials
-// of p_new . q.
+// The new search direction and its product in one launch: (r.z)_new =
+// r.D^-1.r + r_c.y_c from the one-block sums, beta = (r.z)_new /
+// scal[prv]; block 0 publishes (r.z)_new in scal[cur].  The operands of a row's
+// product do not depend on these scalars, so the first row's loads are issued
+// before them.  A row group forms the direction of every column it touches
+// with the same operations as the column's own row, which alone stores it
+// (p_old and p_new are two buffers); q = K p_new and partials of p_new . q.
 template <int L, bool LOOP>
 __global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, const int32_t* ecol, const double* zd,
-                                                          const uint8_t* chif, const double* p_old, double* p_new,
-                                                          double* q, const double* part, int np, double* scal,
-                                                          int cur, int prv, int first, long nrows,
+                                                          const int32_t* cmap, const double* yc, int nc,
+                                                          const double* p_old, double* p_new, double* q,
+                                                          double* scal, int cur, int prv, int first, long nrows,
                                                           double* part_pap) {
   __shared__ double sh[8];
-  __shared__ double bc[3];
+  __shared__ double ys[kCoarseMax];
   const int lane = threadIdx.x % L;
   const long groups = (long)gridDim.x * (blockDim.x / L);
   long row = (long)blockIdx.x * (blockDim.x / L) + threadIdx.x / L;
   EllRow e;
-  ell_row_load<L>(e, row, lane, nrows, eval, ecol, zd, chif, p_old);
-  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) {
-    s1 += part[i];
-    s2 += part[kRedBlocks + i];
-    s3 += part[2 * kRedBlocks + i];
-  }
-  const double t1 = block_sum(s1, sh);
-  const double t2 = block_sum(s2, sh);
-  const double t3 = block_sum(s3, sh);
-  if (threadIdx.x == 0) {
-    bc[0] = t1;
-    bc[1] = t2;
-    bc[2] = t3;
-  }
-  __syncthreads();
-  const double E = scal[S_E];
-  const double cc = (E > 0.0) ? bc[2] / E : 0.0;
-  const double rz_new = bc[0] + cc * bc[2];
+  ell_row_load<L>(e, row, lane, nrows, eval, ecol, zd, cmap, p_old);
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) ys[c] = yc[c];
+  const double rz_new = scal[S_RDR] + scal[S_RZC];
   const double rz = first ? 0.0 : scal[prv];
   const double beta = (!first && rz != 0.0) ? rz_new / rz : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    scal[S_CC] = cc;
-    scal[cur] = rz_new;
-    scal[S_RR] = bc[1];
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[cur] = rz_new;
+  __syncthreads();
   double acc = 0.0;
   // LOOP = false: the grid has a row group for every row (fewer live registers
   // than the loop's prefetch of the next row, two waves per SIMD instead of one)
   for (; row < nrows; row += groups) {
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < kEllSlots; ++k) s += e.val[k] * cg_dir(e.zd[k], e.po[k], e.cf[k], cc, beta);
+    for (int k = 0; k < kEllSlots; ++k) s += e.val[k] * cg_dir(e.zd[k], e.po[k], e.cm[k], ys, beta);
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, L);
     if (lane == 0) {
-      const double pi = cg_dir(e.zd_own, e.po_own, e.cf_own, cc, beta);
+      const double pi = cg_dir(e.zd_own, e.po_own, e.cm_own, ys, beta);
       p_new[row] = pi;
       q[row] = s;
       acc += pi * s;
     }
     if (!LOOP) break;
-    ell_row_load<L>(e, row + groups, lane, nrows, eval, ecol, zd, chif, p_old);
+    ell_row_load<L>(e, row + groups, lane, nrows, eval, ecol, zd, cmap, p_old);
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) part_pap[blockIdx.x] = t;
@@ -636,12 +816,23 @@ struct Work {
   double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double *v = nullptr, *t = nullptr, *r0 = nullptr, *dinv = nullptr;
   // Krylov iterations (allocated on the first solve): the ELL copy of the
-  // masked matrix (ell_lanes lanes per row), the second direction buffer,
-  // D^-1 r and the chi flags of the solve's mask
+  // masked matrix (ell_lanes lanes per row), the second direction buffer and
+  // D^-1 r
   int ell_lanes = 0;
   int32_t* ell_col = nullptr;
   double *ell_val = nullptr, *p2 = nullptr, *zd = nullptr;
-  uint8_t* chif = nullptr;
+  // two-level preconditioner: n_agg node aggregates, n_coarse = n_agg * nd
+  // coarse dofs; cmap0 the coarse dof of every dof, cmap the same with -1 on
+  // the solve's Dirichlet dofs; agg_ptr / agg_dofs the dofs of each aggregate;
+  // the n_seg coarse nonzeros (seg_key = row * n_coarse + column) with the
+  // matrix entries that sum to each (seg_ptr, seg_e, and their rows seg_row);
+  // A_c, the transpose of its inverse, y_c and the update kernel's partials
+  // of the restriction
+  bool krylov_ready = false;
+  int n_agg = 0, n_coarse = 0, upd_sub = 1, n_seg = 0;
+  int32_t *cmap0 = nullptr, *cmap = nullptr, *agg_ptr = nullptr, *agg_dofs = nullptr;
+  int32_t *seg_ptr = nullptr, *seg_key = nullptr, *seg_e = nullptr, *seg_row = nullptr;
+  double *Ac = nullptr, *AinvT = nullptr, *yc = nullptr, *partc = nullptr;
   double *ub = nullptr, *phib = nullptr;
   double *part = nullptr, *scal = nullptr, *hscal = nullptr;
   uint8_t* mask = nullptr;
@@ -673,7 +864,9 @@ void release_newton_work(gedmg_ctx* c) {
       Work& w = h[i]->w;
       void* ptrs[] = {w.K, w.Kmp, w.R, w.Rmp, w.kt, w.ktmp, w.b, w.x, w.r, w.z, w.p, w.q,
                       w.v, w.t, w.r0, w.dinv, w.ub, w.phib, w.part, w.scal, w.mask,
-                      w.al_uh, w.al_dp, w.al_a, w.al_y, w.ell_col, w.ell_val, w.p2, w.zd, w.chif};
+                      w.al_uh, w.al_dp, w.al_a, w.al_y, w.ell_col, w.ell_val, w.p2, w.zd,
+                      w.cmap0, w.cmap, w.agg_ptr, w.agg_dofs, w.seg_ptr, w.seg_key, w.seg_e, w.seg_row,
+                      w.Ac, w.AinvT, w.yc, w.partc};
       for (void* p : ptrs)
         if (p) (void)hipFree(p);
       if (w.hscal) (void)hipHostFree(w.hscal);
@@ -704,7 +897,7 @@ int ensure_work(gedmg_ctx* c, Work** out) {
       al(&w.z, w.ndof) || al(&w.p, w.ndof) || al(&w.q, w.ndof) || al(&w.v, w.ndof) ||
       al(&w.t, w.ndof) || al(&w.r0, w.ndof) || al(&w.dinv, w.ndof) ||
       al(&w.ub, (long)c->dim * c->n_nodes) || al(&w.phib, c->n_nodes) ||
-      al(&w.part, 3 * kRedBlocks + kEllMaxBlocks) || al(&w.scal, S_NSLOTS) ||
+      al(&w.part, std::max(3 * kRedBlocks, 2 * kUpdMaxBlocks) + kEllMaxBlocks) || al(&w.scal, S_NSLOTS) ||
       hipMalloc((void**)&w.mask, std::max(w.ndof, 1L)) ||
       hipHostMalloc((void**)&w.hscal, sizeof(double) * S_NSLOTS, 0)) {
     c->err = "device allocation for the Newton workspace failed";
@@ -720,9 +913,15 @@ int grid_for(long n) { return (int)std::min<long>(kRedBlocks, (n + kThreads - 1)
 // The ELL column layout of the CSR pattern, built on the first Krylov solve:
 // the lane count is the smallest power of two whose kEllSlots slots per lane
 // hold the longest row.
+// The Krylov layouts, built on the first solve: the ELL column layout of the
+// CSR pattern (the lane count is the smallest power of two whose kEllSlots
+// slots per lane hold the longest row) and the two-level preconditioner's
+// aggregates: the mesh's bounding box cut into k^dim boxes, k the largest
+// with k^dim * nd <= kCoarseMax, one aggregate per box that holds a node.
 int ensure_ell(gedmg_ctx* c, Work& w) {
-  if (w.ell_col) return GEDMG_OK;
+  if (w.krylov_ready) return GEDMG_OK;
   const long n = w.ndof;
+  const int nd = c->dim + 1, nn = c->n_nodes, dim = c->dim;
   std::vector<int32_t> rp(n + 1);
   GH(hipMemcpy(rp.data(), c->drowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
   int longest = 1;
@@ -734,23 +933,114 @@ int ensure_ell(gedmg_ctx* c, Work& w) {
              std::to_string(kEllMaxLanes * kEllSlots) + " entries";
     return GEDMG_E_ARG;
   }
+  // aggregates
+  std::vector<double> X((size_t)dim * nn);
+  GH(hipMemcpy(X.data(), c->dX, sizeof(double) * X.size(), hipMemcpyDeviceToHost));
+  int k = 1;
+  while (true) {
+    long cells = 1;
+    for (int d = 0; d < dim; ++d) cells *= (k + 1);
+    if (cells * nd > kCoarseMax) break;
+    ++k;
+  }
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int d = 0; d < dim; ++d) {
+    lo[d] = hi[d] = nn ? X[(size_t)d * nn] : 0.0;
+    for (int i = 0; i < nn; ++i) {
+      lo[d] = std::min(lo[d], X[(size_t)d * nn + i]);
+      hi[d] = std::max(hi[d], X[(size_t)d * nn + i]);
+    }
+  }
+  std::vector<int> box(nn);
+  for (int i = 0; i < nn; ++i) {
+    int b = 0;
+    for (int d = dim - 1; d >= 0; --d) {
+      const double ext = hi[d] - lo[d];
+      int q = ext > 0.0 ? (int)((X[(size_t)d * nn + i] - lo[d]) / ext * k) : 0;
+      q = std::min(std::max(q, 0), k - 1);
+      b = b * k + q;
+    }
+    box[i] = b;
+  }
+  long ncell = 1;
+  for (int d = 0; d < dim; ++d) ncell *= k;
+  std::vector<int> agg_of_box(ncell, -1);
+  int n_agg = 0;
+  for (int i = 0; i < nn; ++i)
+    if (agg_of_box[box[i]] < 0) agg_of_box[box[i]] = n_agg++;  // numbered by first node
+  const int nc = n_agg * nd;
+  std::vector<int32_t> cmap0(n), agg_ptr(n_agg + 1, 0), agg_dofs(n);
+  for (long i = 0; i < n; ++i) {
+    const int a = agg_of_box[box[i / nd]];
+    cmap0[i] = a * nd + (int)(i % nd);
+    agg_ptr[a + 1]++;
+  }
+  for (int a = 0; a < n_agg; ++a) agg_ptr[a + 1] += agg_ptr[a];
+  {
+    std::vector<int32_t> fill(agg_ptr.begin(), agg_ptr.end() - 1);
+    for (long i = 0; i < n; ++i) agg_dofs[fill[cmap0[i] / nd]++] = (int32_t)i;
+  }
+  // coarse nonzeros: the CSR entries counting-sorted by (coarse row, coarse column)
+  const long nnz = rp[n];
+  std::vector<int32_t> col(nnz);
+  GH(hipMemcpy(col.data(), c->dcol, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+  std::vector<int32_t> cnt((size_t)nc * nc + 1, 0);
+  for (long i = 0; i < n; ++i)
+    for (long e = rp[i]; e < rp[i + 1]; ++e) cnt[(size_t)cmap0[i] * nc + cmap0[col[e]] + 1]++;
+  for (size_t q = 0; q < (size_t)nc * nc; ++q) cnt[q + 1] += cnt[q];
+  std::vector<int32_t> seg_e(nnz), seg_row(nnz);
+  {
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (long i = 0; i < n; ++i)
+      for (long e = rp[i]; e < rp[i + 1]; ++e) {
+        const int32_t pos = fill[(size_t)cmap0[i] * nc + cmap0[col[e]]]++;
+        seg_e[pos] = (int32_t)e;
+        seg_row[pos] = (int32_t)i;
+      }
+  }
+  std::vector<int32_t> seg_ptr(1, 0), seg_key;
+  for (size_t q = 0; q < (size_t)nc * nc; ++q)
+    if (cnt[q + 1] > cnt[q]) {
+      seg_key.push_back((int32_t)q);
+      seg_ptr.push_back(cnt[q + 1]);
+    }
+  const int n_seg = (int)seg_key.size();
+  const int sub = std::max(1, std::min(kUpdTailMax / std::max(n_agg, 1), (512 + n_agg - 1) / std::max(n_agg, 1)));
+
   const long slots = (long)L * kEllSlots * std::max(n, 1L);
-  if (hipMalloc((void**)&w.ell_col, sizeof(int32_t) * slots) || hipMalloc((void**)&w.ell_val, sizeof(double) * slots) ||
-      hipMalloc((void**)&w.p2, sizeof(double) * std::max(n, 1L)) ||
-      hipMalloc((void**)&w.zd, sizeof(double) * std::max(n, 1L)) || hipMalloc((void**)&w.chif, std::max(n, 1L))) {
+  const long n1 = std::max(n, 1L), nnz1 = std::max(nnz, 1L);
+  auto ai = [&](int32_t** p, long m) { return hipMalloc((void**)p, sizeof(int32_t) * std::max(m, 1L)); };
+  auto ad = [&](double** p, long m) { return hipMalloc((void**)p, sizeof(double) * std::max(m, 1L)); };
+  if (ai(&w.ell_col, slots) || ad(&w.ell_val, slots) || ad(&w.p2, n1) || ad(&w.zd, n1) || ai(&w.cmap0, n1) ||
+      ai(&w.cmap, n1) || ai(&w.agg_ptr, n_agg + 1) || ai(&w.agg_dofs, n1) || ai(&w.seg_ptr, n_seg + 1) ||
+      ai(&w.seg_key, n_seg) || ai(&w.seg_e, nnz1) || ai(&w.seg_row, nnz1) ||
+      ad(&w.Ac, (long)nc * nc) || ad(&w.AinvT, (long)nc * nc) || ad(&w.yc, kCoarseMax) ||
+      ad(&w.partc, 4L * kUpdMaxBlocks)) {
     c->err = "device allocation for the Krylov workspace failed";
-    for (void* q : {(void*)w.ell_col, (void*)w.ell_val, (void*)w.p2, (void*)w.zd, (void*)w.chif})
-      if (q) (void)hipFree(q);
-    w.ell_col = nullptr;
-    w.ell_val = w.p2 = w.zd = nullptr;
-    w.chif = nullptr;
+    int32_t** ip[] = {&w.ell_col, &w.cmap0, &w.cmap, &w.agg_ptr, &w.agg_dofs, &w.seg_ptr, &w.seg_key, &w.seg_e,
+                      &w.seg_row};
+    double** dp[] = {&w.ell_val, &w.p2, &w.zd, &w.Ac, &w.AinvT, &w.yc, &w.partc};
+    for (auto q : ip) { if (*q) (void)hipFree(*q); *q = nullptr; }
+    for (auto q : dp) { if (*q) (void)hipFree(*q); *q = nullptr; }
     return GEDMG_E_NOMEM;
   }
+  GH(hipMemcpy(w.cmap0, cmap0.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  GH(hipMemcpy(w.agg_ptr, agg_ptr.data(), sizeof(int32_t) * (n_agg + 1), hipMemcpyHostToDevice));
+  GH(hipMemcpy(w.agg_dofs, agg_dofs.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  GH(hipMemcpy(w.seg_ptr, seg_ptr.data(), sizeof(int32_t) * (n_seg + 1), hipMemcpyHostToDevice));
+  GH(hipMemcpy(w.seg_key, seg_key.data(), sizeof(int32_t) * n_seg, hipMemcpyHostToDevice));
+  GH(hipMemcpy(w.seg_e, seg_e.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+  GH(hipMemcpy(w.seg_row, seg_row.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+  w.n_agg = n_agg;
+  w.n_coarse = nc;
+  w.n_seg = n_seg;
+  w.upd_sub = sub;
   w.ell_lanes = L;
   if (n > 0)
     hipLaunchKernelGGL(ell_cols_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->drowptr, c->dcol, n, L,
                        w.ell_col);
   GH(hipGetLastError());
+  w.krylov_ready = true;
   return GEDMG_OK;
 }
 
@@ -782,14 +1072,14 @@ int ell_grid(const Work& w) {
     default: hipLaunchKernelGGL((KERNEL<64, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
   }
 
-// The ELL values of the masked matrix K and the chi flags of w.mask (at the
+// The ELL values of the masked matrix K and the coarse map of w.mask (at the
 // start of every Krylov solve).
 int ell_pack(gedmg_ctx* c, Work& w, const double* K) {
   int rc = ensure_ell(c, w);
   if (rc) return rc;
   if (w.ndof > 0)
     hipLaunchKernelGGL(ell_pack_kernel, dim3((w.ndof + 255) / 256), dim3(256), 0, c->stream, K, c->drowptr, w.mask,
-                       c->dim + 1, w.ndof, w.ell_lanes, w.ell_val, w.chif);
+                       w.cmap0, w.ndof, w.ell_lanes, w.ell_val, w.cmap);
   GH(hipGetLastError());
   return GEDMG_OK;
 }
@@ -797,7 +1087,7 @@ int ell_pack(gedmg_ctx* c, Work& w, const double* K) {
 // y = K x with the ELL copy of the last ell_pack, scal[slot] = w . y
 int ell_spmv(gedmg_ctx* c, Work& w, const double* x, double* y, const double* wv, int slot) {
   const int gs = ell_grid(w);
-  double* part = w.part + 3 * kRedBlocks;
+  double* part = w.part + std::max(3 * kRedBlocks, 2 * kUpdMaxBlocks);
   ELL_LAUNCH(ell_spmv_kernel, w.ell_lanes, gs, w.ell_val, w.ell_col, x, y, wv, w.ndof, part);
   GH(hipGetLastError());
   if (slot >= 0) {
@@ -856,22 +1146,23 @@ int read_scalars(gedmg_ctx* c, Work& w) {
 // Solve K x = b (CG with the Jacobi + coarse preconditioner; BiCGStab with
 // Jacobi on non-positive curvature).  K is the masked matrix and w.mask the
 // Dirichlet mask of this solve.  Returns iterations in *its.
-// CG in two launches per iteration: the new search direction with its product
-// from the ELL copy (and partials of p.q), then the update (and partials of
-// r.D^-1.r, r.r and chi.r).  The host polls the residual adaptively (each poll
-// stalls the stream, so the next one is placed at 70 % of the iterations that
-// the observed decay rate still needs, 8 to 128 ahead).  The ELL copy of K is
-// packed by the caller.
+// CG with the two-level preconditioner.  Per solve: A_c from the masked matrix
+// and its dense inverse.  Per iteration three launches: the new search
+// direction with its product from the ELL copy (and partials of p.q), the
+// update over the aggregates, and the one-block sums that form the scalars
+// and the coarse correction for the next direction.  The host polls the residual adaptively
+// (each poll stalls the stream, so the next one is placed at 70 % of the
+// iterations that the observed decay rate still needs, 8 to 128 ahead).  The
+// ELL copy of K and the coarse map are packed by the caller.
 // Sets *curvature on non-positive curvature; *bb_out receives b.b.
 int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int* its, bool* curvature,
              double* bb_out) {
   const long n = w.ndof;
-  const int gr = kRedBlocks;
-  const int gu = grid_for(n);
   const int gs = ell_grid(w);
   const bool loop = (long)gs * (kThreads / w.ell_lanes) < n;
-  const int nd = c->dim + 1;
-  double* part_pap = w.part + 3 * kRedBlocks;
+  const int nd = c->dim + 1, nc = w.n_coarse;
+  const int gu = w.n_agg * w.upd_sub;
+  double* part_pap = w.part + std::max(3 * kRedBlocks, 2 * kUpdMaxBlocks);
   double* pbuf[2] = {w.p, w.p2};
   int rc;
   *its = 0;
@@ -879,13 +1170,17 @@ int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, in
   GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
   GH(hipMemsetAsync(w.p, 0, sizeof(double) * n, c->stream));  // p_old of the first iteration
   GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
+  GH(hipMemsetAsync(w.Ac, 0, sizeof(double) * nc * nc, c->stream));
   GH(hipMemcpyAsync(w.r, w.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-  hipLaunchKernelGGL(coarse_energy_kernel, dim3(gr), dim3(kThreads), 0, c->stream, K, c->drowptr, c->dcol,
-                     w.mask, nd, n, w.part);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part, w.scal, S_E, -1, kRedBlocks);
-  hipLaunchKernelGGL(cg_init_kernel, dim3(gu), dim3(kThreads), 0, c->stream, w.r, w.dinv, w.chif, n, w.part, w.zd);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part + kRedBlocks, w.scal, S_RR, -1,
-                     gu);
+  if (w.n_seg > 0)
+    hipLaunchKernelGGL(coarse_matrix_kernel, dim3(w.n_seg), dim3(256), 0, c->stream, K, c->dcol, w.seg_ptr,
+                       w.seg_key, w.seg_e, w.seg_row, w.mask, w.Ac);
+  hipLaunchKernelGGL(coarse_invert_kernel, dim3(1), dim3(1024), 0, c->stream, w.Ac, nc, w.AinvT, w.scal);
+  // the first residual's scalars and coarse correction (x and r unchanged)
+  hipLaunchKernelGGL(cg_update_kernel, dim3(gu), dim3(kThreads), 0, c->stream, w.x, w.r, w.p, w.q, w.dinv, w.zd,
+                     w.agg_ptr, w.agg_dofs, w.upd_sub, nd, part_pap, 0, w.scal, S_RZ, 1, w.part, w.partc);
+  hipLaunchKernelGGL(coarse_tail_kernel, dim3(1), dim3(1024), 0, c->stream, w.part, w.partc, gu, w.upd_sub, nd,
+                     nc, w.AinvT, w.scal, w.yc);
   GH(hipGetLastError());
   if ((rc = read_scalars(c, w))) return rc;
   const double bb = w.hscal[S_RR];
@@ -902,21 +1197,19 @@ int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, in
     double* p_old = pbuf[(it - 1) & 1];
     double* p_new = pbuf[it & 1];
     if (loop) {
-      ELL_LAUNCH_T(cg_dir_spmv_kernel, w.ell_lanes, true, gs, w.ell_val, w.ell_col, w.zd, w.chif, p_old, p_new, w.q,
-                   w.part, gu, w.scal, cur, prv, (int)(it == 1), n, part_pap);
+      ELL_LAUNCH_T(cg_dir_spmv_kernel, w.ell_lanes, true, gs, w.ell_val, w.ell_col, w.zd, w.cmap, w.yc, nc, p_old,
+                   p_new, w.q, w.scal, cur, prv, (int)(it == 1), n, part_pap);
     } else {
-      ELL_LAUNCH_T(cg_dir_spmv_kernel, w.ell_lanes, false, gs, w.ell_val, w.ell_col, w.zd, w.chif, p_old, p_new, w.q,
-                   w.part, gu, w.scal, cur, prv, (int)(it == 1), n, part_pap);
+      ELL_LAUNCH_T(cg_dir_spmv_kernel, w.ell_lanes, false, gs, w.ell_val, w.ell_col, w.zd, w.cmap, w.yc, nc, p_old,
+                   p_new, w.q, w.scal, cur, prv, (int)(it == 1), n, part_pap);
     }
     hipLaunchKernelGGL(cg_update_kernel, dim3(gu), dim3(kThreads), 0, c->stream, w.x, w.r, p_new, w.q, w.dinv,
-                       w.chif, w.scal, cur, n, part_pap, gs, w.part, w.zd);
+                       w.zd, w.agg_ptr, w.agg_dofs, w.upd_sub, nd, part_pap, gs, w.scal, cur, 0, w.part, w.partc);
+    hipLaunchKernelGGL(coarse_tail_kernel, dim3(1), dim3(1024), 0, c->stream, w.part, w.partc, gu, w.upd_sub,
+                       nd, nc, w.AinvT, w.scal, w.yc);
     GH(hipGetLastError());
     *its = it;
     if (it == next_poll || it == max_it) {
-      // r.r of the updated residual
-      hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, c->stream, w.part + kRedBlocks, w.scal, S_RR,
-                         -1, gu);
-      GH(hipGetLastError());
       if ((rc = read_scalars(c, w))) return rc;
       if (w.hscal[S_FLAG] != 0.0) { *curvature = true; return GEDMG_OK; }
       const double rr = w.hscal[S_RR];

@@ -210,8 +210,12 @@ def test_full_size_adjoint_directional_derivative():
     reaction targets from the seeded perturbed weights, gradient at the seeded
     weights.  Its directional derivative along a random direction (entries
     scaled by max(1, |theta|)) against a central difference of the GPU loss
-    with step 1e-3; measured agreement about 1e-6 (the loss carries about 1e-9
-    relative noise from the converged states, truncation is O(h^2))."""
+    with step 1e-2.  The converged states of the load path are determined to
+    the Newton tolerance (1e-10 of each step's first residual), which leaves
+    about 1e-7 relative noise in the loss (the loss moves by that much when
+    only the Krylov preconditioner changes); the difference quotient divides
+    it by the step, about 1e-4 at step 1e-3, and 1e-5 at 1e-2, where the
+    truncation error is about 6e-6."""
     from paper_2604_03411_amd import gedmg as G
     case = W.make_case(5)
     steps = case.n_steps
@@ -235,7 +239,7 @@ def test_full_size_adjoint_directional_derivative():
     de = rng.standard_normal(te.size) * np.maximum(1.0, np.abs(te)) / np.sqrt(n_all)
     dy = rng.standard_normal(ty.size) * np.maximum(1.0, np.abs(ty)) / np.sqrt(n_all)
     gd = float(ge @ de + gy @ dy)
-    h = 1e-3
+    h = 1e-2
     vals = []
     for sgn in (1, -1):
         ctx.set_params(te + sgn * h * de, ty + sgn * h * dy)
