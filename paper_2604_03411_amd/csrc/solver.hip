@@ -31,7 +31,6 @@ constexpr int kEllMaxBlocks = 8192;  // grid cap of the ELL products (partials)
 // is formed in LDS), and the aggregate-aligned update kernel's grid.
 constexpr int kCoarseMax = 128;
 constexpr int kUpdMaxBlocks = 1024;
-constexpr int kUpdTailMax = 640;  // update blocks whose partials the tail stages in LDS
 constexpr int kMaxBacktracks = 12;  // halvings of one Newton correction
 constexpr int kThreads = 256;
 
@@ -314,22 +313,20 @@ __global__ __launch_bounds__(256) void coarse_matrix_kernel(const double* K, con
   if (threadIdx.x == 0) Ac[seg_key[seg]] = t;
 }
 
-// Gauss-Jordan inverse of A_c (nc <= kCoarseMax) with partial pivoting, one
-// block of 1024 threads: thread t owns row t / 8, columns t % 8 + 8 m, in
-// registers.  Rows are not interchanged: column k's pivot is the largest
-// |A[i][k]| over the rows not yet used as pivots (p_k, lowest index on ties),
-// and the in-place elimination then leaves P with A^-1[a][b] =
-// P[p_a][q_b], q the inverse of p.  A coarse dof without free dofs has a zero
-// row and column and gets a unit diagonal.  Writes the transpose of the
-// inverse (for coalesced products); a zero pivot sets scal[S_FLAG + 2] and
-// leaves the coarse correction out (zero inverse).
+// Gauss-Jordan inverse of A_c (nc <= kCoarseMax) in one block of 1024
+// threads: thread t owns row t / 8, columns t % 8 + 8 m, in registers.  No
+// pivoting (A_c is symmetric positive definite for a symmetric positive
+// definite tangent, and Gauss-Jordan without interchanges is stable there); a
+// pivot not above 1e-13 of the largest diagonal entry of A_c sets
+// scal[S_FLAG + 2] and leaves the coarse correction out (zero inverse).  A
+// coarse dof without free dofs has a zero row and column and gets a unit
+// diagonal.  Writes the transpose of the inverse (for coalesced products).
 __global__ __launch_bounds__(1024) void coarse_invert_kernel(const double* Ac, int nc, double* AinvT, double* scal) {
   constexpr int M = kCoarseMax / 8;
-  __shared__ double P[kCoarseMax * kCoarseMax];
+  __shared__ double prow[2][kCoarseMax];
   __shared__ double colk[2][kCoarseMax];
-  __shared__ double prow[kCoarseMax];
-  __shared__ int pk[kCoarseMax], qk[kCoarseMax], used[kCoarseMax];
-  __shared__ int piv_row, singular;
+  __shared__ double dmax_w[16];
+  __shared__ int singular;
   const int t = threadIdx.x;
   const int ti = t >> 3, tj = t & 7;
   const bool own = ti < nc;
@@ -339,15 +336,26 @@ __global__ __launch_bounds__(1024) void coarse_invert_kernel(const double* Ac, i
     const int j = tj + 8 * m;
     a[m] = (own && j < nc) ? Ac[ti * nc + j] : 0.0;
   }
-  // a coarse dof without free dofs: unit diagonal (its row and column are zero)
+  double dmax = 0.0;
 #pragma unroll
   for (int m = 0; m < M; ++m)
-    if (own && tj + 8 * m == ti && a[m] == 0.0) a[m] = 1.0;
-  if (t < kCoarseMax) used[t] = 0;
+    if (own && tj + 8 * m == ti) {
+      if (a[m] == 0.0) a[m] = 1.0;  // a coarse dof without free dofs
+      dmax = fabs(a[m]);
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+  if ((t & 63) == 0) dmax_w[t >> 6] = dmax;
   if (t == 0) singular = 0;
   __syncthreads();
+  double dm = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) dm = fmax(dm, dmax_w[w]);
+  const double tiny = 1e-13 * dm;
   for (int k = 0; k < nc; ++k) {
+    double* pr = prow[k & 1];
     double* ck = colk[k & 1];
+    // column k of every row, and row k scaled by its pivot (in-place: the
+    // pivot's own entry becomes 1 / pivot)
     if (own && tj == (k & 7)) {
       double v = 0.0;
 #pragma unroll
@@ -356,78 +364,43 @@ __global__ __launch_bounds__(1024) void coarse_invert_kernel(const double* Ac, i
       ck[ti] = v;
     }
     __syncthreads();
-    if (t < 64) {  // pivot search by one wavefront
-      double bv = -1.0;
-      int bi = nc;
-      for (int i = t; i < nc; i += 64)
-        if (!used[i]) {
-          const double v = fabs(ck[i]);
-          if (v > bv || (v == bv && i < bi)) {
-            bv = v;
-            bi = i;
-          }
-        }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(bv, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ov > bv || (ov == bv && oi < bi)) {
-          bv = ov;
-          bi = oi;
-        }
-      }
-      if (t == 0) {
-        if (!(bv > 0.0) || bi >= nc) {
-          singular = 1;
-        } else {
-          piv_row = bi;
-          used[bi] = 1;
-          pk[k] = bi;
-          qk[bi] = k;
-        }
-      }
+    const double piv = ck[k];
+    if (!(fabs(piv) > tiny)) {
+      if (t == 0) singular = 1;
+      break;
     }
-    __syncthreads();
-    if (singular) break;
-    const int p = piv_row;
-    const double pivinv = 1.0 / ck[p];
-    if (ti == p) {
+    const double pivinv = 1.0 / piv;
+    if (ti == k) {
 #pragma unroll
       for (int m = 0; m < M; ++m) {
         const int j = tj + 8 * m;
         const double v = (j == k ? 1.0 : a[m]) * pivinv;
         a[m] = v;
-        if (j < nc) prow[j] = v;
+        if (j < nc) pr[j] = v;
       }
     }
     __syncthreads();
-    if (own && ti != p) {
+    if (own && ti != k) {
       const double f = ck[ti];
 #pragma unroll
       for (int m = 0; m < M; ++m) {
         const int j = tj + 8 * m;
-        if (j < nc) a[m] = (j == k ? 0.0 : a[m]) - f * prow[j];
+        if (j < nc) a[m] = (j == k ? 0.0 : a[m]) - f * pr[j];
       }
     }
   }
+  __syncthreads();
   if (singular) {
     for (int i = t; i < nc * nc; i += blockDim.x) AinvT[i] = 0.0;
     if (t == 0) scal[S_FLAG + 2] = 1.0;
     return;
   }
-  __syncthreads();
   if (own) {
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       const int j = tj + 8 * m;
-      if (j < nc) P[ti * nc + j] = a[m];
+      if (j < nc) AinvT[j * nc + ti] = a[m];
     }
-  }
-  __syncthreads();
-  // A^-1[r][c] = P[p_r][q_c], stored transposed: AinvT[c * nc + r]
-  for (int idx = t; idx < nc * nc; idx += blockDim.x) {
-    const int c = idx / nc, r = idx - c * nc;
-    AinvT[idx] = P[pk[r] * nc + qk[c]];
   }
 }
 
@@ -532,51 +505,76 @@ __global__ __launch_bounds__(256) void cg_update_kernel(double* x, double* r, co
 // One block of 1024 threads: the update kernel's nb partials summed in a fixed
 // order into r.D^-1.r (scal[S_RDR]) and r.r (scal[S_RR]), the restriction r_c
 // = P^T r, the coarse correction y_c = A_c^-1 r_c (yc) and r_c.y_c
-// (scal[S_RZC]).  A_c^-1 and the restriction's partials are staged in LDS
-// with coalesced loads first.
+// (scal[S_RZC]).  Thread t serves coarse dof t % 128 and an eighth (t / 128)
+// of each sum; the eighths are added in order.
 __global__ __launch_bounds__(1024) void coarse_tail_kernel(const double* part, const double* partc, int nb, int sub,
                                                            int nd, int nc, const double* AinvT, double* scal,
                                                            double* yc) {
-  __shared__ double Ai[kCoarseMax * kCoarseMax];
-  __shared__ double pc[4 * kUpdTailMax];
+  __shared__ double ph[8][kCoarseMax];
   __shared__ double rcs[kCoarseMax];
   __shared__ double sh[3][16];
   const int t = threadIdx.x;
-  for (int i = t; i < nc * nc; i += blockDim.x) Ai[i] = AinvT[i];
-  for (int i = t; i < 4 * nb; i += blockDim.x) pc[i] = partc[i];
+  const int c = t & (kCoarseMax - 1), q = t >> 7;
+  // this thread's entries of A_c^-1 first (they do not depend on the sums):
+  // rows j = q + 8 m of column c, addresses clamped into the matrix
+  constexpr int M = kCoarseMax / 8;
+  double ai[M];
+  {
+    const int cc = c < nc ? c : nc - 1;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int j = q + 8 * m;
+      ai[m] = AinvT[(j < nc ? j : nc - 1) * nc + cc];
+    }
+  }
   double S1 = 0.0, S2 = 0.0;
   for (int b = t; b < nb; b += blockDim.x) {
     S1 += part[b];
     S2 += part[kUpdMaxBlocks + b];
   }
+  if (c < nc) {
+    const int ag = c / nd, comp = c - ag * nd;
+    double v = 0.0;
+    for (int j = q; j < sub; j += 8) v += partc[(ag * sub + j) * 4 + comp];
+    ph[q][c] = v;
+  }
   __syncthreads();
   if (t < nc) {
-    const int ag = t / nd, comp = t - ag * nd;
     double v = 0.0;
-    for (int j = 0; j < sub; ++j) v += pc[(ag * sub + j) * 4 + comp];
+    for (int qq = 0; qq < 8; ++qq) v += ph[qq][t];
     rcs[t] = v;
+  }
+  __syncthreads();
+  if (c < nc) {
+    double y = 0.0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int j = q + 8 * m;
+      if (j < nc) y += ai[m] * rcs[j];
+    }
+    ph[q][c] = y;
   }
   __syncthreads();
   double rzc = 0.0;
   if (t < nc) {
     double y = 0.0;
-    for (int j = 0; j < nc; ++j) y += Ai[j * nc + t] * rcs[j];
+    for (int qq = 0; qq < 8; ++qq) y += ph[qq][t];
     yc[t] = y;
     rzc = rcs[t] * y;
   }
   // the three sums: wavefront shuffles, then the 16 wavefronts in order
   double v[3] = {S1, S2, rzc};
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int k = 0; k < 3; ++k) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
-    if ((t & 63) == 0) sh[q][t >> 6] = v[q];
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    if ((t & 63) == 0) sh[k][t >> 6] = v[k];
   }
   __syncthreads();
   if (t == 0) {
     double T[3] = {0.0, 0.0, 0.0};
-    for (int q = 0; q < 3; ++q)
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) T[q] += sh[q][w];
+    for (int k = 0; k < 3; ++k)
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) T[k] += sh[k][w];
     scal[S_RDR] = T[0];
     scal[S_RR] = T[1];
     scal[S_RZC] = T[2];
@@ -1005,7 +1003,7 @@ int ensure_ell(gedmg_ctx* c, Work& w) {
       seg_ptr.push_back(cnt[q + 1]);
     }
   const int n_seg = (int)seg_key.size();
-  const int sub = std::max(1, std::min(kUpdTailMax / std::max(n_agg, 1), (512 + n_agg - 1) / std::max(n_agg, 1)));
+  const int sub = std::max(1, std::min(kUpdMaxBlocks / std::max(n_agg, 1), (512 + n_agg - 1) / std::max(n_agg, 1)));
 
   const long slots = (long)L * kEllSlots * std::max(n, 1L);
   const long n1 = std::max(n, 1L), nnz1 = std::max(nnz, 1L);
