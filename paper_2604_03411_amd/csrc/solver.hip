@@ -52,9 +52,8 @@ gedmg_solver_opts default_solver_opts() {
 }
 
 // Device scalar slots (doubles).
-// S_FLAG + 1 holds sums read back by the host, S_FLAG + 2 flags a singular
-// coarse matrix; S_RDR = r.D^-1.r and S_RZC = r_c . A_c^-1 r_c of the current
-// CG residual (r.z = S_RDR + S_RZC).
+// S_FLAG + 1 holds sums read back by the host; S_RDR = r.D^-1.r and S_RZC =
+// r_c . A_c^-1 r_c of the current CG residual (r.z = S_RDR + S_RZC).
 enum Slot { S_RZ = 0, S_PAP, S_ALPHA, S_BETA, S_RR, S_BB, S_RHO, S_OMEGA, S_TT, S_TS, S_VR, S_RZNEW,
             S_FLAG, S_RDR = 15, S_RZC = 16, S_NSLOTS = 17 };
 
@@ -317,11 +316,11 @@ __global__ __launch_bounds__(256) void coarse_matrix_kernel(const double* K, con
 // threads: thread t owns row t / 8, columns t % 8 + 8 m, in registers.  No
 // pivoting (A_c is symmetric positive definite for a symmetric positive
 // definite tangent, and Gauss-Jordan without interchanges is stable there); a
-// pivot not above 1e-13 of the largest diagonal entry of A_c sets
-// scal[S_FLAG + 2] and leaves the coarse correction out (zero inverse).  A
+// pivot not above 1e-13 of the largest diagonal entry of A_c leaves the coarse
+// correction out of this solve (zero inverse: plain Jacobi).  A
 // coarse dof without free dofs has a zero row and column and gets a unit
 // diagonal.  Writes the transpose of the inverse (for coalesced products).
-__global__ __launch_bounds__(1024) void coarse_invert_kernel(const double* Ac, int nc, double* AinvT, double* scal) {
+__global__ __launch_bounds__(1024) void coarse_invert_kernel(const double* Ac, int nc, double* AinvT) {
   constexpr int M = kCoarseMax / 8;
   __shared__ double prow[2][kCoarseMax];
   __shared__ double colk[2][kCoarseMax];
@@ -392,7 +391,6 @@ __global__ __launch_bounds__(1024) void coarse_invert_kernel(const double* Ac, i
   __syncthreads();
   if (singular) {
     for (int i = t; i < nc * nc; i += blockDim.x) AinvT[i] = 0.0;
-    if (t == 0) scal[S_FLAG + 2] = 1.0;
     return;
   }
   if (own) {
@@ -906,8 +904,6 @@ int ensure_work(gedmg_ctx* c, Work** out) {
   return GEDMG_OK;
 }
 
-int grid_for(long n) { return (int)std::min<long>(kRedBlocks, (n + kThreads - 1) / kThreads); }
-
 // The ELL column layout of the CSR pattern, built on the first Krylov solve:
 // the lane count is the smallest power of two whose kEllSlots slots per lane
 // hold the longest row.
@@ -1173,7 +1169,7 @@ int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, in
   if (w.n_seg > 0)
     hipLaunchKernelGGL(coarse_matrix_kernel, dim3(w.n_seg), dim3(256), 0, c->stream, K, c->dcol, w.seg_ptr,
                        w.seg_key, w.seg_e, w.seg_row, w.mask, w.Ac);
-  hipLaunchKernelGGL(coarse_invert_kernel, dim3(1), dim3(1024), 0, c->stream, w.Ac, nc, w.AinvT, w.scal);
+  hipLaunchKernelGGL(coarse_invert_kernel, dim3(1), dim3(1024), 0, c->stream, w.Ac, nc, w.AinvT);
   // the first residual's scalars and coarse correction (x and r unchanged)
   hipLaunchKernelGGL(cg_update_kernel, dim3(gu), dim3(kThreads), 0, c->stream, w.x, w.r, w.p, w.q, w.dinv, w.zd,
                      w.agg_ptr, w.agg_dofs, w.upd_sub, nd, part_pap, 0, w.scal, S_RZ, 1, w.part, w.partc);
