@@ -136,8 +136,9 @@ typedef struct {
    * are tested absolutely); 0 makes the test purely relative to ||R_f^0||, for
    * states whose whole residual is scaled by a tiny degradation f_d. */
   double newton_rscale;
-  /* Krylov method of the Newton solves: 0 (default) CG with the Jacobi + coarse
-   * preconditioner, switching to BiCGStab when it meets non-positive curvature
+  /* Krylov method of the Newton solves: 0 (default) CG with the two-level
+   * preconditioner (Jacobi plus a coarse correction on node aggregates of the
+   * mesh's bounding box), switching to BiCGStab when it meets non-positive curvature
    * or reaches max_krylov without converging (each switch counts in
    * krylov_fallbacks); 1 BiCGStab with Jacobi from the start, for tangents that
    * are not symmetric (gamma_d != 1, or points yielding with kappa below
@@ -270,7 +271,8 @@ int gedmg_status(gedmg_ctx* ctx);
  *   2. sets the prescribed dofs bc (device dof / value arrays);
  *   3. runs Newton on the free dofs, with a preconditioned Krylov solve of
  *      K_ff d = -R_f per iteration (CG with Jacobi plus a coarse correction on
- *      the uniform damage field; BiCGStab with Jacobi when CG meets
+ *      node aggregates, whose span holds the uniform damage field; BiCGStab
+ *      with Jacobi when CG meets
  *      non-positive curvature on a non-symmetric or indefinite tangent), a
  *      correction that inverts an element being halved (up to 12 times), until
  *      ||R_f|| <= max(newton_rtol max(newton_rscale, ||R_f^0||), newton_atol);
