@@ -172,3 +172,17 @@ def test_coarse_space_with_dirichlet_aggregates_matches_oracle():
     assert rel_err(phi.cpu().numpy(), po) <= 1e-6
     assert rel_err(kap.cpu().numpy(), kt) <= 1e-6
     ctx.close()
+
+
+def test_newton_path_is_bitwise_reproducible():
+    """The Krylov kernels sum every partial in a fixed order (no atomics), so
+    two runs of the same load steps give bitwise-identical states: the 16x16
+    notched plate, 4 steps, twice in fresh contexts."""
+    from paper_2604_03411_amd import gedmg as G
+    case = W.make_case(3, n=16)
+    du = W.uniaxial_increment(case)
+    print("[newton] notched q4 16x16, 4 steps, twice", flush=True)
+    runs = [run_gpu_path(G, case, 4, W.uniaxial_bc, predictor_du=du) for _ in range(2)]
+    for (u1, p1, k1, r1), (u2, p2, k2, r2) in zip(*runs):
+        assert np.array_equal(u1, u2) and np.array_equal(p1, p2) and np.array_equal(k1, k2)
+        assert r1["krylov_iters"] == r2["krylov_iters"] and r1["reaction"] == r2["reaction"]
