@@ -140,7 +140,7 @@ typedef struct {
    * preconditioner (Jacobi plus a coarse correction on node aggregates of the
    * mesh's bounding box), switching to BiCGStab when it meets non-positive curvature
    * or reaches max_krylov without converging (each switch counts in
-   * krylov_fallbacks); 1 BiCGStab with Jacobi from the start, for tangents that
+   * krylov_fallbacks); 1 BiCGStab (same preconditioner) from the start, for tangents that
    * are not symmetric (gamma_d != 1, or points yielding with kappa below
    * kappa_d, where the history enters the damage rows but not the displacement
    * rows). */
@@ -272,7 +272,7 @@ int gedmg_status(gedmg_ctx* ctx);
  *   3. runs Newton on the free dofs, with a preconditioned Krylov solve of
  *      K_ff d = -R_f per iteration (CG with Jacobi plus a coarse correction on
  *      node aggregates, whose span holds the uniform damage field; BiCGStab
- *      with Jacobi when CG meets
+ *      with the same preconditioner when CG meets
  *      non-positive curvature on a non-symmetric or indefinite tangent), a
  *      correction that inverts an element being halved (up to 12 times), until
  *      ||R_f|| <= max(newton_rtol max(newton_rscale, ||R_f^0||), newton_atol);

@@ -717,12 +717,13 @@ __global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, co
   if (threadIdx.x == 0) part_pap[blockIdx.x] = t;
 }
 
-__global__ void precond_kernel(double* z, const double* r, const double* dinv, long n) {
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    z[i] = dinv[i] * r[i];
+// z += P y_c (the coarse correction's prolongation; -1 marks a Dirichlet dof)
+__global__ void coarse_prolong_kernel(double* z, const int32_t* cmap, const double* yc, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && cmap[i] >= 0) z[i] += yc[cmap[i]];
 }
 
-// ---- BiCGStab pieces (right Jacobi preconditioning)
+// ---- BiCGStab pieces (right preconditioning with the two-level M)
 // p = r + beta (p - omega v), beta = (rho_new/rho) (alpha/omega)
 __global__ void bicg_p_kernel(double* p, const double* r, const double* v, const double* scal, long n) {
   const double beta = scal[S_BETA], omega = scal[S_OMEGA];
@@ -1140,8 +1141,38 @@ int read_scalars(gedmg_ctx* c, Work& w) {
 // Solve K x = b (CG with the Jacobi + coarse preconditioner; BiCGStab with
 // Jacobi on non-positive curvature).  K is the masked matrix and w.mask the
 // Dirichlet mask of this solve.  Returns iterations in *its.
-// CG with the two-level preconditioner.  Per solve: A_c from the masked matrix
-// and its dense inverse.  Per iteration three launches: the new search
+// A_c = P^T K P from the masked matrix and its dense inverse (once per Krylov
+// solve, after the ELL copy and the coarse map of the solve's mask).
+int coarse_setup(gedmg_ctx* c, Work& w, const double* K) {
+  const int nc = w.n_coarse;
+  GH(hipMemsetAsync(w.Ac, 0, sizeof(double) * nc * nc, c->stream));
+  if (w.n_seg > 0)
+    hipLaunchKernelGGL(coarse_matrix_kernel, dim3(w.n_seg), dim3(256), 0, c->stream, K, c->dcol, w.seg_ptr,
+                       w.seg_key, w.seg_e, w.seg_row, w.mask, w.Ac);
+  hipLaunchKernelGGL(coarse_invert_kernel, dim3(1), dim3(1024), 0, c->stream, w.Ac, nc, w.AinvT);
+  GH(hipGetLastError());
+  return GEDMG_OK;
+}
+
+// z = M^-1 x with the two-level preconditioner: D^-1 x and the restriction
+// P^T x over the aggregates (the update kernel in its first-residual mode, x
+// in the place of r), y_c = A_c^-1 P^T x, then z += P y_c.  Overwrites the
+// update kernel's partials and the scalars S_RDR, S_RR and S_RZC.
+int apply_two_level(gedmg_ctx* c, Work& w, const double* x, double* z) {
+  const long n = w.ndof;
+  const int nd = c->dim + 1, nc = w.n_coarse, gu = w.n_agg * w.upd_sub;
+  hipLaunchKernelGGL(cg_update_kernel, dim3(gu), dim3(kThreads), 0, c->stream, nullptr, const_cast<double*>(x),
+                     nullptr, nullptr, w.dinv, z, w.agg_ptr, w.agg_dofs, w.upd_sub, nd, nullptr, 0, w.scal, S_RZ, 1,
+                     w.part, w.partc);
+  hipLaunchKernelGGL(coarse_tail_kernel, dim3(1), dim3(1024), 0, c->stream, w.part, w.partc, gu, w.upd_sub, nd, nc,
+                     w.AinvT, w.scal, w.yc);
+  hipLaunchKernelGGL(coarse_prolong_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, z, w.cmap, w.yc, n);
+  GH(hipGetLastError());
+  return GEDMG_OK;
+}
+
+// CG with the two-level preconditioner (A_c^-1 formed by the caller).  Per
+// iteration three launches: the new search
 // direction with its product from the ELL copy (and partials of p.q), the
 // update over the aggregates, and the one-block sums that form the scalars
 // and the coarse correction for the next direction.  The host polls the residual adaptively
@@ -1164,12 +1195,7 @@ int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, in
   GH(hipMemsetAsync(w.x, 0, sizeof(double) * n, c->stream));
   GH(hipMemsetAsync(w.p, 0, sizeof(double) * n, c->stream));  // p_old of the first iteration
   GH(hipMemsetAsync(w.scal, 0, sizeof(double) * S_NSLOTS, c->stream));
-  GH(hipMemsetAsync(w.Ac, 0, sizeof(double) * nc * nc, c->stream));
   GH(hipMemcpyAsync(w.r, w.b, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-  if (w.n_seg > 0)
-    hipLaunchKernelGGL(coarse_matrix_kernel, dim3(w.n_seg), dim3(256), 0, c->stream, K, c->dcol, w.seg_ptr,
-                       w.seg_key, w.seg_e, w.seg_row, w.mask, w.Ac);
-  hipLaunchKernelGGL(coarse_invert_kernel, dim3(1), dim3(1024), 0, c->stream, w.Ac, nc, w.AinvT);
   // the first residual's scalars and coarse correction (x and r unchanged)
   hipLaunchKernelGGL(cg_update_kernel, dim3(gu), dim3(kThreads), 0, c->stream, w.x, w.r, w.p, w.q, w.dinv, w.zd,
                      w.agg_ptr, w.agg_dofs, w.upd_sub, nd, part_pap, 0, w.scal, S_RZ, 1, w.part, w.partc);
@@ -1231,7 +1257,8 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
   *its = 0;
   double bb = 0.0;
   {
-    const int rcp = ell_pack(c, w, K);
+    int rcp = ell_pack(c, w, K);
+    if (!rcp) rcp = coarse_setup(c, w, K);
     if (rcp) return rcp;
   }
   if (method == 1) {  // BiCGStab requested (non-symmetric tangents)
@@ -1258,7 +1285,7 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
     if (!(rc1 == GEDMG_E_LINSOLVE && *its >= max_it) && (rc1 || !curvature)) return rc1;
     if (fallbacks) ++*fallbacks;
   }
-  // BiCGStab from x = 0 with right Jacobi preconditioning.
+  // BiCGStab from x = 0, right-preconditioned with the two-level M.
   int rc;
   const int check = 8;
   const double tol2 = rtol * rtol * bb;
@@ -1281,11 +1308,11 @@ int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int*
     if ((rc = dot2(c, w, w.r0, w.r, nullptr, nullptr, S_RZNEW, -1))) return rc;
     hipLaunchKernelGGL(bicg_scalars_kernel, dim3(1), dim3(1), 0, c->stream, w.scal, 0);
     hipLaunchKernelGGL(bicg_p_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.p, w.r, w.v, w.scal, n);
-    hipLaunchKernelGGL(precond_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.z, w.p, w.dinv, n);  // phat
+    if ((rc = apply_two_level(c, w, w.p, w.z))) return rc;  // phat
     if ((rc = ell_spmv(c, w, w.z, w.v, w.r0, S_VR))) return rc;                                            // v = K phat
     hipLaunchKernelGGL(bicg_scalars_kernel, dim3(1), dim3(1), 0, c->stream, w.scal, 1);
     hipLaunchKernelGGL(bicg_s_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.r, w.v, w.scal, n);     // s in r
-    hipLaunchKernelGGL(precond_kernel, dim3(gr), dim3(kThreads), 0, c->stream, w.q, w.r, w.dinv, n);  // shat
+    if ((rc = apply_two_level(c, w, w.r, w.q))) return rc;  // shat
     if ((rc = ell_spmv(c, w, w.q, w.t, nullptr, -1))) return rc;                                         // t = K shat
     if ((rc = dot2(c, w, w.t, w.t, w.t, w.r, S_TT, S_TS))) return rc;
     hipLaunchKernelGGL(bicg_scalars_kernel, dim3(1), dim3(1), 0, c->stream, w.scal, 2);
