@@ -1250,13 +1250,15 @@ int cg_multi(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, in
   return GEDMG_E_LINSOLVE;
 }
 
+// reuse = true: K, the mask and D^-1 are those of the previous call, whose
+// ELL copy and coarse inverse are kept.
 int krylov(gedmg_ctx* c, Work& w, const double* K, int max_it, double rtol, int* its, int method = 0,
-           int* fallbacks = nullptr) {
+           int* fallbacks = nullptr, bool reuse = false) {
   const long n = w.ndof;
   const int gr = kRedBlocks;
   *its = 0;
   double bb = 0.0;
-  {
+  if (!reuse) {
     int rcp = ell_pack(c, w, K);
     if (!rcp) rcp = coarse_setup(c, w, K);
     if (rcp) return rcp;
@@ -1386,8 +1388,8 @@ int solver_solve_free(gedmg_ctx* c, double* A, const gedmg_dirichlet* bc, const 
     hipLaunchKernelGGL(masked_residual_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, rhs, w.q, w.mask,
                        w.b, n);
     GH(hipGetLastError());
-    int more = 0;
-    if ((rc = krylov(c, w, A, max_it, rtol_pass, &more))) return rc;
+    int more = 0;  // same matrix and mask: the ELL copy and the coarse inverse are kept
+    if ((rc = krylov(c, w, A, max_it, rtol_pass, &more, 0, nullptr, true))) return rc;
     *its += more;
     hipLaunchKernelGGL(add_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, x, w.x, n);
     GH(hipGetLastError());
@@ -1766,7 +1768,8 @@ extern "C" int gedmg_arclength_step(gedmg_ctx* c, const gedmg_dirichlet* pattern
     hipLaunchKernelGGL(masked_neg_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, w.al_y, w.mask, w.b, n);
     GH(hipGetLastError());
     int its = 0;
-    rc = krylov(c, w, w.K, o.max_krylov, eta, &its, o.krylov_method, &r.krylov_fallbacks);  // b in w.x
+    // b in w.x; same matrix and mask as the solve for a: the ELL copy and the coarse inverse are kept
+    rc = krylov(c, w, w.K, o.max_krylov, eta, &its, o.krylov_method, &r.krylov_fallbacks, true);
     r.krylov_iters_total += its;
     if (rc) return rollback(rc);
     double da = 0.0, db = 0.0;
