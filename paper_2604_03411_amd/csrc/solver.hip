@@ -288,7 +288,8 @@ __global__ void reduce_kernel(const double* part, double* scal, int slot, int sl
 // (1 - d kappa / d phi), orders of magnitude below the rest of the spectrum),
 // and the aggregates' smooth modes that set Jacobi-CG's iteration count.  A_c
 // (at most kCoarseMax dofs) is assembled and inverted densely at the start of
-// every solve.  z = M^-1 r is never stored: the update kernel leaves D^-1 r
+// a solve (a solve with the previous one's matrix keeps it); BiCGStab applies
+// the same M.  In CG z = M^-1 r is never stored: the update kernel leaves D^-1 r
 // and partials, a one-block kernel the coarse correction y_c = A_c^-1 P^T r
 // with the scalars r.D^-1.r, r_c.y_c and r.r, and the direction kernel forms z
 // on the fly.  r.z of the current and of the previous direction alternate
