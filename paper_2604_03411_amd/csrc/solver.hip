@@ -581,15 +581,27 @@ __global__ __launch_bounds__(1024) void coarse_tail_kernel(const double* part, c
 }
 
 // ---- ELL copy of the masked matrix for the Krylov iterations.  Slot s of a
-// row (its s-th CSR entry, or a zero on the row's own column past its length)
-// is stored at ((s / L) * nrows + row) * L + s % L: the L lanes of a row and
-// consecutive rows read consecutive words, and no row length is loaded.
-__global__ void ell_cols_kernel(const int32_t* rowptr, const int32_t* col, long nrows, int L, int32_t* ecol) {
-  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= nrows) return;
-  const int j0 = rowptr[row], len = rowptr[row + 1] - j0;
-  for (int s = 0; s < L * kEllSlots; ++s)
-    ecol[((long)(s / L) * nrows + row) * L + s % L] = s < len ? col[j0 + s] : (int32_t)row;
+// row (its s-th CSR entry, or a zero past its length) is stored at
+// ((s / L) * nrows + row) * L + s % L: the L lanes of a row and consecutive
+// rows read consecutive words, and no row length is loaded.  The columns are
+// not stored per entry: the pattern is made of nd x nd node blocks, every row
+// of node a has the columns (b, 0..nd-1) of its neighbour nodes b in order, so
+// slot s lies in column nbr(a, s / nd) * nd + s mod nd.  ncol holds nbr(a, t)
+// at t * n_nodes + a, and a itself past the neighbour count (the padding
+// slots then fall on the row's own node block, with value zero).
+__global__ void ell_ncols_kernel(const int32_t* rowptr, const int32_t* col, long nn, int nd, int nbmax,
+                                 int32_t* ncol) {
+  const long a = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nn) return;
+  const int j0 = rowptr[a * nd], deg = (rowptr[a * nd + 1] - j0) / nd;
+  for (int t = 0; t < nbmax; ++t) ncol[(long)t * nn + a] = t < deg ? col[j0 + t * nd] / nd : (int32_t)a;
+}
+
+// column of slot k of lane `lane` in row group of node a (see ell_ncols_kernel)
+template <int L, int ND>
+__device__ __forceinline__ int32_t ell_col(const int32_t* ncol, long nn, long a, int k, int lane) {
+  const int s = k * L + lane;
+  return ncol[(long)(s / ND) * nn + a] * ND + s % ND;
 }
 
 // ELL values of K, and the coarse dof of every free dof (-1 on Dirichlet dofs)
@@ -604,21 +616,21 @@ __global__ void ell_pack_kernel(const double* K, const int32_t* rowptr, const ui
   cmap[row] = mask[row] ? -1 : cmap0[row];
 }
 
-// y = K x from the ELL copy (L lanes per row) and partials of w . y
-template <int L>
-__global__ __launch_bounds__(256) void ell_spmv_kernel(const double* eval, const int32_t* ecol, const double* x,
+// y = K x from the ELL copy (L lanes per row, ND dofs per node) and partials of w . y
+template <int L, int ND>
+__global__ __launch_bounds__(256) void ell_spmv_kernel(const double* eval, const int32_t* ncol, const double* x,
                                                        double* y, const double* w, long nrows, double* part) {
+  const long nn = nrows / ND;
   __shared__ double sh[8];
   const int lane = threadIdx.x % L;
   const long groups = (long)gridDim.x * (blockDim.x / L);
   double acc = 0.0;
   for (long row = (long)blockIdx.x * (blockDim.x / L) + threadIdx.x / L; row < nrows; row += groups) {
     double s = 0.0;
+    const long a = row / ND;
 #pragma unroll
-    for (int k = 0; k < kEllSlots; ++k) {
-      const long idx = ((long)k * nrows + row) * L + lane;
-      s += eval[idx] * x[ecol[idx]];
-    }
+    for (int k = 0; k < kEllSlots; ++k)
+      s += eval[((long)k * nrows + row) * L + lane] * x[ell_col<L, ND>(ncol, nn, a, k, lane)];
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, L);
     if (lane == 0) {
@@ -640,17 +652,17 @@ struct EllRow {
   int32_t cm_own;
 };
 
-template <int L>
+template <int L, int ND>
 __device__ __forceinline__ void ell_row_load(EllRow& e, long row, int lane, long nrows, const double* eval,
-                                             const int32_t* ecol, const double* zd, const int32_t* cmap,
+                                             const int32_t* ncol, const double* zd, const int32_t* cmap,
                                              const double* p_old) {
   if (row >= nrows) return;
+  const long nn = nrows / ND, a = row / ND;
   int col[kEllSlots];
 #pragma unroll
   for (int k = 0; k < kEllSlots; ++k) {
-    const long idx = ((long)k * nrows + row) * L + lane;
-    col[k] = ecol[idx];
-    e.val[k] = eval[idx];
+    col[k] = ell_col<L, ND>(ncol, nn, a, k, lane);
+    e.val[k] = eval[((long)k * nrows + row) * L + lane];
   }
 #pragma unroll
   for (int k = 0; k < kEllSlots; ++k) {
@@ -677,8 +689,8 @@ __device__ __forceinline__ double cg_dir(double zd, double po, int32_t cm, const
 // before them.  A row group forms the direction of every column it touches
 // with the same operations as the column's own row, which alone stores it
 // (p_old and p_new are two buffers); q = K p_new and partials of p_new . q.
-template <int L, bool LOOP>
-__global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, const int32_t* ecol, const double* zd,
+template <int L, int ND, bool LOOP>
+__global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, const int32_t* ncol, const double* zd,
                                                           const int32_t* cmap, const double* yc, int nc,
                                                           const double* p_old, double* p_new, double* q,
                                                           double* scal, int cur, int prv, int first, long nrows,
@@ -689,7 +701,7 @@ __global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, co
   const long groups = (long)gridDim.x * (blockDim.x / L);
   long row = (long)blockIdx.x * (blockDim.x / L) + threadIdx.x / L;
   EllRow e;
-  ell_row_load<L>(e, row, lane, nrows, eval, ecol, zd, cmap, p_old);
+  ell_row_load<L, ND>(e, row, lane, nrows, eval, ncol, zd, cmap, p_old);
   for (int c = threadIdx.x; c < nc; c += blockDim.x) ys[c] = yc[c];
   const double rz_new = scal[S_RDR] + scal[S_RZC];
   const double rz = first ? 0.0 : scal[prv];
@@ -712,7 +724,7 @@ __global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, co
       acc += pi * s;
     }
     if (!LOOP) break;
-    ell_row_load<L>(e, row + groups, lane, nrows, eval, ecol, zd, cmap, p_old);
+    ell_row_load<L, ND>(e, row + groups, lane, nrows, eval, ncol, zd, cmap, p_old);
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) part_pap[blockIdx.x] = t;
@@ -1004,10 +1016,11 @@ int ensure_ell(gedmg_ctx* c, Work& w) {
   const int sub = std::max(1, std::min(kUpdMaxBlocks / std::max(n_agg, 1), (512 + n_agg - 1) / std::max(n_agg, 1)));
 
   const long slots = (long)L * kEllSlots * std::max(n, 1L);
+  const long nbmax = ((long)L * kEllSlots - 1) / nd + 1;
   const long n1 = std::max(n, 1L), nnz1 = std::max(nnz, 1L);
   auto ai = [&](int32_t** p, long m) { return hipMalloc((void**)p, sizeof(int32_t) * std::max(m, 1L)); };
   auto ad = [&](double** p, long m) { return hipMalloc((void**)p, sizeof(double) * std::max(m, 1L)); };
-  if (ai(&w.ell_col, slots) || ad(&w.ell_val, slots) || ad(&w.p2, n1) || ad(&w.zd, n1) || ai(&w.cmap0, n1) ||
+  if (ai(&w.ell_col, nbmax * std::max(nn, 1)) || ad(&w.ell_val, slots) || ad(&w.p2, n1) || ad(&w.zd, n1) || ai(&w.cmap0, n1) ||
       ai(&w.cmap, n1) || ai(&w.agg_ptr, n_agg + 1) || ai(&w.agg_dofs, n1) || ai(&w.seg_ptr, n_seg + 1) ||
       ai(&w.seg_key, n_seg) || ai(&w.seg_e, nnz1) || ai(&w.seg_row, nnz1) ||
       ad(&w.Ac, (long)nc * nc) || ad(&w.AinvT, (long)nc * nc) || ad(&w.yc, kCoarseMax) ||
@@ -1032,9 +1045,9 @@ int ensure_ell(gedmg_ctx* c, Work& w) {
   w.n_seg = n_seg;
   w.upd_sub = sub;
   w.ell_lanes = L;
-  if (n > 0)
-    hipLaunchKernelGGL(ell_cols_kernel, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->drowptr, c->dcol, n, L,
-                       w.ell_col);
+  if (nn > 0)
+    hipLaunchKernelGGL(ell_ncols_kernel, dim3((nn + 255) / 256), dim3(256), 0, c->stream, c->drowptr, c->dcol, nn,
+                       nd, (int)nbmax, w.ell_col);
   GH(hipGetLastError());
   w.krylov_ready = true;
   return GEDMG_OK;
@@ -1047,26 +1060,37 @@ int ell_grid(const Work& w) {
   return (int)std::max(1L, std::min<long>(kEllMaxBlocks, (w.ndof + groups_per_block - 1) / groups_per_block));
 }
 
-#define ELL_LAUNCH(KERNEL, L, GRID, ...)                                                                   \
-  switch (L) {                                                                                             \
-    case 1: hipLaunchKernelGGL((KERNEL<1>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
-    case 2: hipLaunchKernelGGL((KERNEL<2>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
-    case 4: hipLaunchKernelGGL((KERNEL<4>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
-    case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
-    case 16: hipLaunchKernelGGL((KERNEL<16>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
-    case 32: hipLaunchKernelGGL((KERNEL<32>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
-    default: hipLaunchKernelGGL((KERNEL<64>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
+// launch KERNEL<L, ND(, T)> for the row lanes L of the ELL copy and the dofs per
+// node of the mesh (3 for Q4, 4 for Hex8)
+#define ELL_CASES(KERNEL, ND, T, GRID, ...)                                                                \
+  switch (L_) {                                                                                            \
+    case 1: hipLaunchKernelGGL((KERNEL<1, ND T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 2: hipLaunchKernelGGL((KERNEL<2, ND T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 4: hipLaunchKernelGGL((KERNEL<4, ND T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 8: hipLaunchKernelGGL((KERNEL<8, ND T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
+    case 16: hipLaunchKernelGGL((KERNEL<16, ND T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
+    case 32: hipLaunchKernelGGL((KERNEL<32, ND T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL((KERNEL<64, ND T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
   }
-#define ELL_LAUNCH_T(KERNEL, L, T, GRID, ...)                                                                   \
-  switch (L) {                                                                                             \
-    case 1: hipLaunchKernelGGL((KERNEL<1, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
-    case 2: hipLaunchKernelGGL((KERNEL<2, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
-    case 4: hipLaunchKernelGGL((KERNEL<4, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
-    case 8: hipLaunchKernelGGL((KERNEL<8, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break;   \
-    case 16: hipLaunchKernelGGL((KERNEL<16, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
-    case 32: hipLaunchKernelGGL((KERNEL<32, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
-    default: hipLaunchKernelGGL((KERNEL<64, T>), dim3(GRID), dim3(kThreads), 0, c->stream, __VA_ARGS__); break; \
-  }
+#define ELL_LAUNCH(KERNEL, L, GRID, ...)                 \
+  do {                                                   \
+    const int L_ = (L);                                  \
+    if (c->dim == 2) {                                   \
+      ELL_CASES(KERNEL, 3, , GRID, __VA_ARGS__)          \
+    } else {                                             \
+      ELL_CASES(KERNEL, 4, , GRID, __VA_ARGS__)          \
+    }                                                    \
+  } while (0)
+#define ELL_LAUNCH_T(KERNEL, L, T, GRID, ...)            \
+  do {                                                   \
+    const int L_ = (L);                                  \
+    if (c->dim == 2) {                                   \
+      ELL_CASES(KERNEL, 3, ELL_COMMA T, GRID, __VA_ARGS__) \
+    } else {                                             \
+      ELL_CASES(KERNEL, 4, ELL_COMMA T, GRID, __VA_ARGS__) \
+    }                                                    \
+  } while (0)
+#define ELL_COMMA ,
 
 // The ELL values of the masked matrix K and the coarse map of w.mask (at the
 // start of every Krylov solve).
