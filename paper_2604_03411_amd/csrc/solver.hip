@@ -597,6 +597,15 @@ __global__ void ell_ncols_kernel(const int32_t* rowptr, const int32_t* col, long
   for (int t = 0; t < nbmax; ++t) ncol[(long)t * nn + a] = t < deg ? col[j0 + t * nd] / nd : (int32_t)a;
 }
 
+// Blocks are dealt to the 8 XCDs round-robin (block b to XCD b mod 8).  The
+// ELL kernels use logical block xcd_block(b) instead, which gives every XCD a
+// contiguous range of row groups, so that the neighbouring rows a row's
+// columns gather are mostly in the same XCD's L2.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // column of slot k of lane `lane` in row group of node a (see ell_ncols_kernel)
 template <int L, int ND>
 __device__ __forceinline__ int32_t ell_col(const int32_t* ncol, long nn, long a, int k, int lane) {
@@ -625,7 +634,8 @@ __global__ __launch_bounds__(256) void ell_spmv_kernel(const double* eval, const
   const int lane = threadIdx.x % L;
   const long groups = (long)gridDim.x * (blockDim.x / L);
   double acc = 0.0;
-  for (long row = (long)blockIdx.x * (blockDim.x / L) + threadIdx.x / L; row < nrows; row += groups) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  for (long row = (long)lb * (blockDim.x / L) + threadIdx.x / L; row < nrows; row += groups) {
     double s = 0.0;
     const long a = row / ND;
 #pragma unroll
@@ -699,7 +709,7 @@ __global__ __launch_bounds__(256) void cg_dir_spmv_kernel(const double* eval, co
   __shared__ double ys[kCoarseMax];
   const int lane = threadIdx.x % L;
   const long groups = (long)gridDim.x * (blockDim.x / L);
-  long row = (long)blockIdx.x * (blockDim.x / L) + threadIdx.x / L;
+  long row = (long)xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / L) + threadIdx.x / L;
   EllRow e;
   ell_row_load<L, ND>(e, row, lane, nrows, eval, ncol, zd, cmap, p_old);
   for (int c = threadIdx.x; c < nc; c += blockDim.x) ys[c] = yc[c];
